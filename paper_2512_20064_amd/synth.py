@@ -1,0 +1,186 @@
+"""Seeded synthetic inputs: random right-canonical matrix product states.
+
+This module only builds inputs.  It holds none of the sampling arithmetic
+(no contraction, no probabilities, no draws); both the FP64 oracle and the
+HIP sampler consume what it returns.
+
+The paper samples MPS produced from Gaussian Boson Sampling data, which are
+not available here.  The stand-in keeps their shape (Section 2.2: a chain of
+M site tensors, physical dimension d, bond dimension chi, the bond growing
+from the open ends, Section 3.4.2) and their decaying photon-number weights:
+
+* G = (N(0,1) + i N(0,1)) / sqrt(2), drawn from PCG64 seeded by
+  (tensor_seed, mps_id, k), shape (chi_l, d, chi_r);
+* physical slice i is multiplied by exp(-i/2);
+* B = Q^H from the reduced QR of G.reshape(chi_l, d*chi_r)^H, with the
+  column phases of Q fixed so that diag(R) is real and non-negative (QR is
+  unique only up to those phases).
+
+B then has orthonormal rows, i.e. sum_i B_i B_i^H = I (right-canonical form),
+which is what the sampler's Lambda-free measurement assumes.
+
+Site tensors are stored as complex arrays of shape (chi_l, d, chi_r):
+row-major [left bond][physical][right bond], so each physical branch of a
+row is a contiguous run of chi_r complex numbers.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# Seed tag that separates pooled plateau tensors from per-site tensors.
+_POOL_TAG = 0x504F4F4C
+
+
+def ramp_bonds(d: list[int], chi_max: int) -> list[int]:
+    """Bond dimensions chi_0..chi_M of an open chain with a bond cap.
+
+    chi_k = min(chi_max, prod_{j<k} d_j, prod_{j>=k} d_j): the largest bond a
+    right-canonical chain with open ends can carry (a row-orthonormal
+    chi_l x d*chi_r matrix needs chi_l <= d*chi_r), capped at chi_max.  This
+    is the edge-to-centre growth of Section 3.4.2 in its exact-simulation
+    form.
+    """
+    M = len(d)
+    chi = []
+    for k in range(M + 1):
+        left = 1
+        for j in range(k):
+            left = min(left * d[j], chi_max)
+        right = 1
+        for j in range(k, M):
+            right = min(right * d[j], chi_max)
+        chi.append(min(chi_max, left, right))
+    return chi
+
+
+def _site_from_gaussian(G: np.ndarray) -> np.ndarray:
+    chi_l, d, chi_r = G.shape
+    G = G * np.exp(-0.5 * np.arange(d))[None, :, None]
+    X = G.reshape(chi_l, d * chi_r).conj().T          # (d*chi_r, chi_l)
+    Q, R = np.linalg.qr(X, mode="reduced")
+    diag = np.diagonal(R)
+    ph = np.where(np.abs(diag) > 0, diag / np.where(diag == 0, 1, np.abs(diag)), 1.0)
+    Q = Q * ph[None, :]
+    return np.ascontiguousarray(Q.conj().T.reshape(chi_l, d, chi_r))
+
+
+def gaussian_site(seed_words: list[int], chi_l: int, d: int, chi_r: int) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed_words)))
+    shape = (chi_l, d, chi_r)
+    re = rng.standard_normal(shape)
+    im = rng.standard_normal(shape)
+    return (re + 1j * im) / np.sqrt(2.0)
+
+
+def random_site(tensor_seed: int, mps_id: int, k: int, chi_l: int, d: int, chi_r: int) -> np.ndarray:
+    """Right-canonical complex128 site tensor (chi_l, d, chi_r) for site k."""
+    if chi_l > d * chi_r:
+        raise ValueError(f"chi_l={chi_l} > d*chi_r={d * chi_r}: no right-canonical tensor")
+    return _site_from_gaussian(gaussian_site([tensor_seed, mps_id, k], chi_l, d, chi_r))
+
+
+def random_mps(tensor_seed: int, d: list[int] | int, chi: list[int], M: int | None = None,
+               mps_id: int = 0, pool: int = 0) -> list[np.ndarray]:
+    """A right-canonical MPS as a list of complex128 (chi_k, d_k, chi_{k+1}) arrays.
+
+    ``pool`` > 0 reuses ``pool`` distinct tensors for every site of a repeated
+    (chi_l, d, chi_r) shape: site k takes pooled tensor k mod pool of its shape.
+    The chain is still right-canonical; the option only bounds generation time
+    and host memory for chains whose distinct tensors would not fit (the list
+    holds shared references; callers that need one device buffer per site
+    upload each entry separately).
+    """
+    if isinstance(d, int):
+        assert M is not None
+        d = [d] * M
+    M = len(d)
+    assert len(chi) == M + 1
+    sites: list[np.ndarray] = []
+    cache: dict[tuple, np.ndarray] = {}
+    for k in range(M):
+        shape = (chi[k], d[k], chi[k + 1])
+        if pool > 0:
+            key = shape + (k % pool,)
+            if key not in cache:
+                G = gaussian_site([tensor_seed, mps_id, _POOL_TAG, *shape, k % pool], *shape)
+                cache[key] = _site_from_gaussian(G)
+            sites.append(cache[key])
+        else:
+            sites.append(random_site(tensor_seed, mps_id, k, *shape))
+    return sites
+
+
+def canonical_error(B: np.ndarray) -> float:
+    """max |sum_i B_i B_i^H - I| for one site tensor (chi_l, d, chi_r)."""
+    chi_l = B.shape[0]
+    X = B.reshape(chi_l, -1)
+    return float(np.max(np.abs(X @ X.conj().T - np.eye(chi_l))))
+
+
+# --------------------------------------------------------------------------
+# Named workloads.  Sizes follow the configurations the sampler is measured
+# on; each returns (tensors, d, chi) with tensors in complex128.
+# --------------------------------------------------------------------------
+
+def small_chain(tensor_seed: int = 1, M: int = 32, d: int = 4, chi_max: int = 32, mps_id: int = 0):
+    """Plain small chain: uniform d, bond cap chi_max, open ends."""
+    dl = [d] * M
+    chi = ramp_bonds(dl, chi_max)
+    return random_mps(tensor_seed, dl, chi, mps_id=mps_id), dl, chi
+
+
+def resident_chain(tensor_seed: int = 3, M: int = 1024, d: int = 4, chi_max: int = 1024,
+                   pool: int = 16, mps_id: int = 0):
+    """GBS-shaped resident chain (M=1024, d=4, chi=1024 by default).
+
+    Ramp sites are distinct; the chi_max x d x chi_max plateau cycles over
+    ``pool`` distinct tensors (1024 distinct QRs of 4096x1024 would take
+    minutes on the host; every site still gets its own device buffer).
+    """
+    dl = [d] * M
+    chi = ramp_bonds(dl, chi_max)
+    return random_mps(tensor_seed, dl, chi, mps_id=mps_id, pool=pool), dl, chi
+
+
+def uneven_chain(tensor_seed: int = 4, M: int = 2048, chi_max: int = 4096, d_lo: int = 2,
+                 d_hi: int = 6, pool: int = 4, mps_id: int = 0):
+    """Chain with per-site physical dimension d_k ~ U{d_lo..d_hi} and ramped bonds."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([tensor_seed, mps_id, 0xD])))
+    dl = [int(x) for x in rng.integers(d_lo, d_hi + 1, size=M)]
+    chi = ramp_bonds(dl, chi_max)
+    return random_mps(tensor_seed, dl, chi, mps_id=mps_id, pool=pool), dl, chi
+
+
+def ensemble_specs(seed: int = 2, B: int = 256, M_lo: int = 32, M_hi: int = 512,
+                   chis=(16, 32, 64, 128, 256), ds=(2, 3, 4)):
+    """(M_b, d_b, chi_max_b) for a batched ensemble of B chains."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 0xE])))
+    out = []
+    for _ in range(B):
+        M = int(rng.integers(M_lo, M_hi + 1))
+        chi = int(rng.choice(chis))
+        d = int(rng.choice(ds))
+        out.append((M, d, chi))
+    return out
+
+
+def to_c64(tensors: list[np.ndarray]) -> list[np.ndarray]:
+    """complex64 casts, sharing casts of shared (pooled) arrays."""
+    seen: dict[int, np.ndarray] = {}
+    out = []
+    for t in tensors:
+        if id(t) not in seen:
+            seen[id(t)] = np.ascontiguousarray(t.astype(np.complex64))
+        out.append(seen[id(t)])
+    return out
+
+
+def promote(tensors: list[np.ndarray]) -> list[np.ndarray]:
+    """complex128 copies of (e.g. complex64) tensors, sharing shared arrays."""
+    seen: dict[int, np.ndarray] = {}
+    out = []
+    for t in tensors:
+        if id(t) not in seen:
+            seen[id(t)] = t.astype(np.complex128)
+        out.append(seen[id(t)])
+    return out
