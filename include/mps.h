@@ -1,0 +1,151 @@
+/*
+ * mps.h -- C ABI of the MI355X MPS sampling sweep (libmps.so).
+ *
+ * The library draws N samples s = (s_0 .. s_{M-1}) from a matrix product
+ * state of M site tensors, one site after the other, for a whole batch of
+ * samples at once: the data-parallel sweep of Section 2.2 (sequential
+ * workflow) and Section 3.1 (data parallelism over samples) of FastMPS,
+ * with the measurement of Section 3.3.1 (Algorithm 1).  At site k every
+ * sample's left vector l (length chi_k) is contracted with the site tensor,
+ *
+ *     W[i][r] = sum_l l[l] * A_k[l][i][r]           (no complex conjugate),
+ *
+ * the branch weights q_i = sum_r |W[i][r]|^2 give the conditional
+ * probabilities q_i / S (S = sum_i q_i), the outcome is the inverse CDF
+ * s = #{ j : u > C_j } at a uniform u, and the left vector becomes
+ * W[s][:] / sqrt(q_s).  Tensors are taken right-canonical
+ * (sum_i A_i A_i^H = I, the Lambda of Algorithm 1 absorbed), so S = 1 up
+ * to rounding; S is nevertheless divided out.
+ *
+ * Uniforms: u = ((x >> 12) + 0.5) * 2^-52 with x the first output word of
+ * Philox4x64-10 (Salmon et al., SC'11) at key (seed, mps_id) and counter
+ * (n, k, 0, 0), n the GLOBAL sample index (n_offset + row).  A sample's
+ * outcomes therefore depend only on (tensors, seed, mps_id, n), never on
+ * how the N samples are chunked, so any range of samples can be drawn,
+ * resumed or sharded independently.
+ *
+ * Status codes: every entry point returns MPS_OK or a negative code;
+ * mps_last_error() gives a message for the calling thread.  Argument
+ * checks run on the host before any HIP call, so MPS_EINVAL is reported
+ * the same way on a machine without a GPU.
+ */
+#ifndef MPS_SAMPLE_H
+#define MPS_SAMPLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MPS_OK = 0,
+  MPS_EINVAL = -1,   /* bad argument; nothing was launched                    */
+  MPS_ENOMEM = -2,   /* scratch would exceed max_device_bytes, or hipMalloc failed */
+  MPS_ENODEV = -3,   /* no HIP device, or the requested ordinal does not exist */
+  MPS_EHIP = -4,     /* a HIP runtime call or a launch failed; message has it  */
+  MPS_ENUMERIC = -5  /* some samples met S <= 0 or a non-finite S; see below   */
+};
+
+/* Arithmetic of the contraction. */
+enum {
+  MPS_FP32 = 0       /* FP32 operands, FP32 MFMA accumulate (v_mfma_f32_32x32x2f32) */
+};
+
+/* Element type of the site tensors. */
+enum {
+  MPS_C64 = 0        /* complex64: (re, im) float pairs, interleaved              */
+};
+
+typedef struct mps_ctx* mps_handle;
+
+typedef struct {
+  int32_t precision;        /* MPS_FP32                                          */
+  int32_t profile;          /* 1: time every kernel launch with HIP events        */
+  int64_t n_chunk;          /* samples per pass over the chain; 0 = planner picks */
+  int64_t max_device_bytes; /* cap on scratch bytes; 0 = no cap                  */
+  void* stream;             /* hipStream_t to run on; NULL = the null stream      */
+  uint64_t mps_id;          /* second key word of the generator (chain id)        */
+  /* Debug emits (device pointers, caller-owned), for the first emit_n samples
+   * of each mps_sample call (rows 0 .. emit_n-1 of the call):
+   *   emit_probs[row][k][i]  conditional probability q_i / S, i < emit_dmax
+   *                          (entries for i >= d_k are left untouched),
+   *   emit_u[row][k]         the uniform u.
+   * Either pointer may be NULL.  emit_n = 0 disables both.                     */
+  int64_t emit_n;
+  int32_t emit_dmax;
+  int32_t reserved;
+  double* emit_probs;
+  double* emit_u;
+} mps_options;
+
+typedef struct {
+  int64_t contract_launches;  /* contraction kernels launched by the last call     */
+  int64_t measure_launches;   /* measurement kernels launched by the last call     */
+  double contract_ms;         /* summed event time of those launches (profile=1)    */
+  double measure_ms;
+  double contract_flops;      /* algorithmic flops: 8 * rows * chi_l * d * chi_r summed */
+  double measure_bytes;       /* algorithmic bytes of the measurement launches      */
+  int64_t n_chunk;            /* chunk size the last call used                      */
+  int64_t flagged;            /* samples that met S <= 0 or non-finite S            */
+  int64_t scratch_bytes;      /* device scratch held by the handle                  */
+} mps_stats;
+
+/* Fill *opt with defaults (FP32, planner chunking, null stream, no emits). */
+int mps_options_init(mps_options* opt);
+
+/* Create a sampler for HIP device `device`.  No HIP call is made here; the
+ * device is first touched by mps_sample.  opt may be NULL (defaults).
+ * Ownership: the handle owns its device scratch; free with mps_destroy. */
+int mps_create(mps_handle* h, int32_t device, const mps_options* opt);
+
+/* Replace the options of a handle (same rules as mps_create). */
+int mps_set_options(mps_handle h, const mps_options* opt);
+
+/*
+ * Draw N samples with global indices n_offset .. n_offset+N-1.
+ *
+ *   tensors   host array of M DEVICE pointers; site k points to a complex
+ *             tensor [chi[k]][d[k]][chi[k+1]], row-major, of element type
+ *             `dtype` (MPS_C64).  Read only.
+ *   chi       host array of M+1 bond dimensions; chi[0] must be 1 (open left
+ *             end); chi[M] may exceed 1 (an open right end whose right
+ *             environment is the identity).  Each chi[k] <= d[k]*chi[k+1]
+ *             (otherwise no right-canonical tensor exists) and
+ *             1 <= chi[k] <= 65536.
+ *   d         host array of M physical dimensions, 1 <= d[k] <= 16.
+ *   M         number of sites, >= 1.   N >= 0 (N = 0 returns MPS_OK).
+ *   n_offset  global index of the first sample, >= 0.
+ *   seed      first key word of the generator.
+ *   outcomes  DEVICE int32 [N][M] row-major (sample-major), caller-owned;
+ *             outcome of sample row at site k.  -1 marks a sample that met
+ *             S <= 0 or a non-finite S at that site or before.
+ *   logp      DEVICE double [N] or NULL: sum over sites of ln(q_s / S), the
+ *             natural log of the sampled configuration's probability; -inf
+ *             for flagged samples.
+ *
+ * Returns MPS_OK, or MPS_ENUMERIC when some samples were flagged (the other
+ * samples are valid; the count is in the message and in mps_stats), or an
+ * error.  The call is synchronous: it returns after the work on the stream
+ * has finished.  The library keeps no pointer to caller memory after it
+ * returns.  One handle must not be used by two threads at once.
+ */
+int mps_sample(mps_handle h, const void* const* tensors, int32_t dtype,
+               const int32_t* chi, const int32_t* d, int32_t M,
+               int64_t N, int64_t n_offset, uint64_t seed,
+               int32_t* outcomes, double* logp);
+
+/* Counters of the last mps_sample call on this handle. */
+int mps_get_stats(mps_handle h, mps_stats* st);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* mps_last_error(void);
+
+/* Free the handle and its scratch.  NULL is ignored. */
+void mps_destroy(mps_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPS_SAMPLE_H */

@@ -60,8 +60,10 @@ def _check_chain(tensors):
 
 
 def sample(tensors, seed: int, N: int, n_offset: int = 0, mps_id: int = 0,
-           forced: np.ndarray | None = None, want_probs: bool = False):
-    """Sample N configurations (global indices n_offset .. n_offset+N-1).
+           forced: np.ndarray | None = None, want_probs: bool = False,
+           n_index: np.ndarray | None = None):
+    """Sample N configurations (global indices n_offset .. n_offset+N-1, or
+    the explicit global indices ``n_index`` when given).
 
     tensors: list of M complex arrays (chi_k, d_k, chi_{k+1}); promoted to
     complex128.  With ``forced`` (int array [N, M]) the chosen branch at each
@@ -81,7 +83,11 @@ def sample(tensors, seed: int, N: int, n_offset: int = 0, mps_id: int = 0,
     _check_chain(tensors)
     M = len(tensors)
     dmax = max(t.shape[1] for t in tensors)
-    n = np.arange(N, dtype=np.uint64) + np.uint64(n_offset)
+    if n_index is not None:
+        n = np.asarray(n_index, dtype=np.uint64)
+        assert n.shape == (N,)
+    else:
+        n = np.arange(N, dtype=np.uint64) + np.uint64(n_offset)
     l = np.ones((N, 1), dtype=np.complex128)
     alive = np.ones(N, dtype=bool)
     logp = np.zeros(N, dtype=np.float64)
@@ -109,6 +115,8 @@ def sample(tensors, seed: int, N: int, n_offset: int = 0, mps_id: int = 0,
         u = uniforms(seed, mps_id, n, k)
         s_orc = draw(C, u)
         s = s_orc if forced is None else np.asarray(forced[:, k], dtype=np.int64)
+        if forced is not None:  # a forced path that stops (-1) or leaves the range stops here
+            ok = ok & (s >= 0) & (s < d)
         s = np.where(ok, s, 0)
         qs = q[rows, s]
         ok = ok & (qs > 0)
@@ -130,10 +138,11 @@ def sample(tensors, seed: int, N: int, n_offset: int = 0, mps_id: int = 0,
     return out
 
 
-def forced_probs(tensors, outcomes: np.ndarray, seed: int, n_offset: int = 0, mps_id: int = 0):
+def forced_probs(tensors, outcomes: np.ndarray, seed: int, n_offset: int = 0, mps_id: int = 0,
+                 n_index: np.ndarray | None = None):
     """Conditional probabilities p_k(i | s_0..s_{k-1}) along given outcomes."""
     return sample(tensors, seed, outcomes.shape[0], n_offset=n_offset, mps_id=mps_id,
-                  forced=outcomes)
+                  forced=outcomes, n_index=n_index)
 
 
 # --------------------------------------------------------------------------

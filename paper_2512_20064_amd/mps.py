@@ -1,0 +1,214 @@
+"""ctypes binding of libmps.so: the C-ABI entry points under the same names.
+
+Argument marshalling only.  Every step of the sampling sweep runs in the HIP
+kernels of libmps.so; there is no Python or CPU fallback.  If the library is
+missing, loading raises instead of degrading.
+
+``Sampler`` is a convenience wrapper that takes torch device tensors (torch
+is used for device memory and streams only).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmps.so")
+
+MPS_OK, MPS_EINVAL, MPS_ENOMEM, MPS_ENODEV, MPS_EHIP, MPS_ENUMERIC = 0, -1, -2, -3, -4, -5
+MPS_FP32 = 0
+MPS_C64 = 0
+
+STATUS_NAMES = {0: "MPS_OK", -1: "MPS_EINVAL", -2: "MPS_ENOMEM", -3: "MPS_ENODEV",
+                -4: "MPS_EHIP", -5: "MPS_ENUMERIC"}
+
+EXPORTS = ("mps_options_init", "mps_create", "mps_set_options", "mps_sample",
+           "mps_get_stats", "mps_last_error", "mps_destroy")
+
+
+class mps_options(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32),
+        ("profile", ctypes.c_int32),
+        ("n_chunk", ctypes.c_int64),
+        ("max_device_bytes", ctypes.c_int64),
+        ("stream", ctypes.c_void_p),
+        ("mps_id", ctypes.c_uint64),
+        ("emit_n", ctypes.c_int64),
+        ("emit_dmax", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("emit_probs", ctypes.c_void_p),
+        ("emit_u", ctypes.c_void_p),
+    ]
+
+
+class mps_stats(ctypes.Structure):
+    _fields_ = [
+        ("contract_launches", ctypes.c_int64),
+        ("measure_launches", ctypes.c_int64),
+        ("contract_ms", ctypes.c_double),
+        ("measure_ms", ctypes.c_double),
+        ("contract_flops", ctypes.c_double),
+        ("measure_bytes", ctypes.c_double),
+        ("n_chunk", ctypes.c_int64),
+        ("flagged", ctypes.c_int64),
+        ("scratch_bytes", ctypes.c_int64),
+    ]
+
+
+class MPSError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libmps.so (raises OSError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError(f"{path} not built: run __graft_entry__.build() or python -m paper_2512_20064_amd.build")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.mps_options_init.argtypes = [ctypes.POINTER(mps_options)]
+    lib.mps_options_init.restype = ctypes.c_int
+    lib.mps_create.argtypes = [ctypes.POINTER(P), ctypes.c_int32, ctypes.POINTER(mps_options)]
+    lib.mps_create.restype = ctypes.c_int
+    lib.mps_set_options.argtypes = [P, ctypes.POINTER(mps_options)]
+    lib.mps_set_options.restype = ctypes.c_int
+    lib.mps_sample.argtypes = [P, ctypes.POINTER(P), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                               ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_int64,
+                               ctypes.c_int64, ctypes.c_uint64, P, P]
+    lib.mps_sample.restype = ctypes.c_int
+    lib.mps_get_stats.argtypes = [P, ctypes.POINTER(mps_stats)]
+    lib.mps_get_stats.restype = ctypes.c_int
+    lib.mps_last_error.argtypes = []
+    lib.mps_last_error.restype = ctypes.c_char_p
+    lib.mps_destroy.argtypes = [P]
+    lib.mps_destroy.restype = None
+    _lib = lib
+    return lib
+
+
+# ---- entry points under their C names --------------------------------------
+
+def mps_last_error() -> str:
+    return load().mps_last_error().decode()
+
+
+def mps_options_init() -> mps_options:
+    o = mps_options()
+    rc = load().mps_options_init(ctypes.byref(o))
+    if rc:
+        raise MPSError(rc, mps_last_error())
+    return o
+
+
+def mps_create(device: int = 0, opt: mps_options | None = None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    rc = load().mps_create(ctypes.byref(h), device, ctypes.byref(opt) if opt is not None else None)
+    if rc:
+        raise MPSError(rc, mps_last_error())
+    return h
+
+
+def mps_set_options(h, opt: mps_options) -> None:
+    rc = load().mps_set_options(h, ctypes.byref(opt))
+    if rc:
+        raise MPSError(rc, mps_last_error())
+
+
+def mps_sample(h, tensor_ptrs, dtype: int, chi, d, M: int, N: int, n_offset: int, seed: int,
+               outcomes_ptr: int, logp_ptr: int | None) -> int:
+    """Raw call; returns the status code (MPS_ENUMERIC is not raised)."""
+    arr = (ctypes.c_void_p * len(tensor_ptrs))(*[ctypes.c_void_p(int(p)) if p else None for p in tensor_ptrs])
+    chi_a = (ctypes.c_int32 * len(chi))(*[int(x) for x in chi])
+    d_a = (ctypes.c_int32 * len(d))(*[int(x) for x in d])
+    return load().mps_sample(h, arr, dtype, chi_a, d_a, M, N, n_offset, ctypes.c_uint64(seed),
+                             ctypes.c_void_p(outcomes_ptr) if outcomes_ptr else None,
+                             ctypes.c_void_p(logp_ptr) if logp_ptr else None)
+
+
+def mps_get_stats(h) -> mps_stats:
+    st = mps_stats()
+    rc = load().mps_get_stats(h, ctypes.byref(st))
+    if rc:
+        raise MPSError(rc, mps_last_error())
+    return st
+
+
+def mps_destroy(h) -> None:
+    load().mps_destroy(h)
+
+
+# ---- convenience wrapper over torch device tensors --------------------------
+
+class Sampler:
+    """Owns an mps handle; samples from complex64 torch tensors on the GPU.
+
+    tensors: list of M torch.complex64 CUDA tensors of shape (chi_k, d_k, chi_{k+1}),
+    contiguous.  Returns (outcomes int32 [N, M], logp float64 [N]) as CUDA tensors.
+    """
+
+    def __init__(self, device: int = 0, n_chunk: int = 0, profile: bool = False,
+                 max_device_bytes: int = 0, mps_id: int = 0, precision: int = MPS_FP32):
+        self.opt = mps_options_init()
+        self.opt.n_chunk = n_chunk
+        self.opt.profile = int(profile)
+        self.opt.max_device_bytes = max_device_bytes
+        self.opt.mps_id = mps_id
+        self.opt.precision = precision
+        self.device = device
+        self.h = mps_create(device, self.opt)
+
+    def close(self):
+        if self.h:
+            mps_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sample(self, tensors, N: int, seed: int, n_offset: int = 0, emit_n: int = 0,
+               emit_dmax: int = 0, want_logp: bool = True, stream=None, raise_numeric: bool = False):
+        import torch
+        dev = torch.device("cuda", self.device)
+        M = len(tensors)
+        chi = [int(tensors[0].shape[0])] + [int(t.shape[2]) for t in tensors]
+        d = [int(t.shape[1]) for t in tensors]
+        for t in tensors:
+            if t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("site tensors must be contiguous complex64 CUDA tensors")
+        outcomes = torch.empty((N, M), dtype=torch.int32, device=dev)
+        logp = torch.empty((N,), dtype=torch.float64, device=dev) if want_logp else None
+        emit_probs = emit_u = None
+        opt = mps_options.from_buffer_copy(self.opt)
+        if emit_n:
+            emit_dmax = emit_dmax or max(d)
+            emit_probs = torch.full((emit_n, M, emit_dmax), float("nan"), dtype=torch.float64, device=dev)
+            emit_u = torch.zeros((emit_n, M), dtype=torch.float64, device=dev)
+            opt.emit_n = emit_n
+            opt.emit_dmax = emit_dmax
+            opt.emit_probs = emit_probs.data_ptr()
+            opt.emit_u = emit_u.data_ptr()
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        opt.stream = s.cuda_stream
+        mps_set_options(self.h, opt)
+        rc = mps_sample(self.h, [t.data_ptr() for t in tensors], MPS_C64, chi, d, M, N, n_offset, seed,
+                        outcomes.data_ptr(), logp.data_ptr() if logp is not None else None)
+        self.status = rc
+        if rc and (rc != MPS_ENUMERIC or raise_numeric):
+            raise MPSError(rc, mps_last_error())
+        self.stats = mps_get_stats(self.h)
+        out = {"outcomes": outcomes, "logp": logp, "status": rc}
+        if emit_n:
+            out["probs"] = emit_probs
+            out["u"] = emit_u
+        return out

@@ -1,0 +1,129 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/*.h, and rejects bad arguments on the host before any
+HIP call."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+from paper_2512_20064_amd import mps
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(mps_\w+)\s*\(", src, flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return mps.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    declared = _declared_functions()
+    assert {"mps_create", "mps_sample", "mps_destroy", "mps_last_error"} <= declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(mps.EXPORTS)
+
+
+def test_options_struct_matches_header():
+    # the binding's struct must have the header's size (8-byte aligned fields)
+    assert ctypes.sizeof(mps.mps_options) == 4 + 4 + 8 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8
+    assert ctypes.sizeof(mps.mps_stats) == 9 * 8
+
+
+def _call(h, **kw):
+    args = dict(tensors=[1, 1], dtype=mps.MPS_C64, chi=[1, 4, 1], d=[4, 4], M=2, N=10, n_offset=0,
+                seed=1, outcomes=1, logp=0)
+    args.update(kw)
+    return mps.mps_sample(h, args["tensors"], args["dtype"], args["chi"], args["d"], args["M"],
+                          args["N"], args["n_offset"], args["seed"], args["outcomes"], args["logp"])
+
+
+@pytest.mark.parametrize("bad", [
+    dict(M=0),
+    dict(N=-1),
+    dict(n_offset=-5),
+    dict(dtype=7),
+    dict(chi=[2, 4, 1]),                    # chi[0] != 1
+    dict(chi=[1, 4, 0]),                    # bond < 1
+    dict(chi=[1, 9, 1]),                    # chi[1] > d[1]*chi[2]: no right-canonical tensor
+    dict(d=[0, 4]),
+    dict(d=[4, 17]),
+    dict(tensors=[1, 0]),                   # NULL site pointer
+    dict(outcomes=0),
+    dict(chi=[1, 70000, 1], d=[16, 16]),    # bond above the supported maximum
+])
+def test_invalid_arguments_rejected_on_host(bad):
+    h = mps.mps_create(0)
+    try:
+        rc = _call(h, **bad)
+        assert rc == mps.MPS_EINVAL, (rc, mps.mps_last_error())
+        assert mps.mps_last_error()
+    finally:
+        mps.mps_destroy(h)
+
+
+def test_null_handle_and_options(lib):
+    assert _call(None) == mps.MPS_EINVAL
+    with pytest.raises(mps.MPSError):
+        mps.mps_create(-1)
+    o = mps.mps_options_init()
+    o.precision = 99
+    with pytest.raises(mps.MPSError) as e:
+        mps.mps_create(0, o)
+    assert e.value.code == mps.MPS_EINVAL
+    o = mps.mps_options_init()
+    o.n_chunk = -3
+    with pytest.raises(mps.MPSError):
+        mps.mps_create(0, o)
+    lib.mps_destroy(None)  # ignored
+
+
+def test_empty_batch_is_ok_without_work():
+    h = mps.mps_create(0)
+    try:
+        assert _call(h, N=0, outcomes=0) == mps.MPS_OK
+        st = mps.mps_get_stats(h)
+        assert st.contract_launches == 0
+    finally:
+        mps.mps_destroy(h)
+
+
+def _gpu_present():
+    try:
+        import torch
+        return torch.cuda.device_count() > 0
+    except Exception:
+        return False
+
+
+@pytest.mark.skipif(_gpu_present(), reason="checks the no-device path")
+def test_no_device_reports_enodev():
+    h = mps.mps_create(0)
+    try:
+        rc = _call(h)
+        assert rc == mps.MPS_ENODEV, (rc, mps.mps_last_error())
+    finally:
+        mps.mps_destroy(h)
+
+
+def test_memory_cap_reports_enomem_before_device():
+    o = mps.mps_options_init()
+    o.max_device_bytes = 1000  # below the scratch of a single sample at these bonds
+    h = mps.mps_create(0, o)
+    try:
+        rc = _call(h, chi=[1, 16, 256, 16, 1], d=[16, 16, 16, 16], M=4, tensors=[1, 1, 1, 1])
+        assert rc == mps.MPS_ENOMEM, (rc, mps.mps_last_error())
+    finally:
+        mps.mps_destroy(h)

@@ -1,0 +1,187 @@
+"""Parity of the HIP sweep (through the C ABI) with the FP64 oracle.
+
+Every case prints what names it before it touches the GPU, so a failing run
+can be attributed from its last output line.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2512_20064_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def mpsmod():
+    from paper_2512_20064_amd import mps
+    mps.load()
+    assert torch.cuda.is_available(), "no GPU visible"
+    return mps
+
+
+def _run(mpsmod, tensors_c64, N, seed, n_offset=0, n_chunk=0, emit_n=0, profile=False):
+    from tests.parity_util import upload
+    dev = upload(tensors_c64)
+    s = mpsmod.Sampler(0, n_chunk=n_chunk, profile=profile)
+    r = s.sample(dev, N, seed, n_offset=n_offset, emit_n=emit_n)
+    torch.cuda.synchronize()
+    out = {"outcomes": r["outcomes"].cpu().numpy(), "logp": r["logp"].cpu().numpy(), "status": r["status"]}
+    if emit_n:
+        out["probs"] = r["probs"].cpu().numpy()
+        out["u"] = r["u"].cpu().numpy()
+    out["stats"] = s.stats
+    s.close()
+    return out
+
+
+def _chain(seed, M, d, chi_max):
+    dl = [d] * M if isinstance(d, int) else d
+    chi = synth.ramp_bonds(dl, chi_max)
+    return synth.to_c64(synth.random_mps(seed, dl, chi))
+
+
+def test_small_chain_parity(mpsmod):
+    """M=32, d=4, chi=32 ramp, N=4096: every row, every site."""
+    from tests.parity_util import compare
+    _say("small chain M=32 d=4 chi=32 N=4096")
+    t = _chain(1, 32, 4, 32)
+    g = _run(mpsmod, t, 4096, seed=1001, emit_n=4096)
+    assert g["status"] == 0
+    rep = compare(t, 1001, g)
+    print(rep)
+
+
+def test_ragged_tiles_and_chunks(mpsmod):
+    """N not a multiple of the 128-row tile, chunk tail, chi_r not a multiple
+    of the 128-column tile, odd bonds (d=3 ramp: 1, 3, 9, 27, 48...)."""
+    from tests.parity_util import compare
+    _say("ragged M=12 d=3 chi=48 N=1000 chunk=384")
+    t = _chain(7, 12, 3, 48)
+    g = _run(mpsmod, t, 1000, seed=77, n_chunk=384, emit_n=1000)
+    rep = compare(t, 77, g)
+    print(rep)
+
+
+def test_several_k_and_column_tiles(mpsmod):
+    """chi=256: 16 K-steps of 16 and two column tiles per branch."""
+    from tests.parity_util import compare
+    _say("chi=256 M=10 d=4 N=1536")
+    t = _chain(8, 10, 4, 256)
+    g = _run(mpsmod, t, 1536, seed=5, emit_n=512)
+    rep = compare(t, 5, g)
+    print(rep)
+
+
+def test_mixed_physical_dims_and_open_right_end(mpsmod):
+    """d_k in {1..6} per site, d=16 site, and chi_M > 1 (identity right environment)."""
+    from tests.parity_util import compare
+    _say("mixed d, d=16 site, open right end")
+    rng = np.random.default_rng(3)
+    dl = [int(x) for x in rng.integers(1, 7, size=9)] + [16]
+    chi = synth.ramp_bonds(dl, 40)
+    chi[-1] = 3  # open right end wider than one
+    chi[-2] = min(chi[-2], dl[-1] * 3)
+    t = synth.to_c64(synth.random_mps(11, dl, chi))
+    g = _run(mpsmod, t, 777, seed=9, emit_n=777)
+    rep = compare(t, 9, g)
+    print(rep)
+
+
+def test_product_state_closed_form(mpsmod):
+    """chi = 1 everywhere: outcomes follow the closed form exactly."""
+    from oracle.philox import uniforms
+    _say("product state chi=1 M=20 d=5 N=3000")
+    rng = np.random.default_rng(4)
+    M, d, N, seed = 20, 5, 3000, 123
+    t = []
+    for k in range(M):
+        a = rng.standard_normal(d) + 1j * rng.standard_normal(d)
+        t.append((a / np.linalg.norm(a)).astype(np.complex64).reshape(1, d, 1))
+    g = _run(mpsmod, t, N, seed)
+    u = uniforms(seed, 0, np.arange(N)[:, None], np.arange(M)[None, :])
+    for k in range(M):
+        p = np.abs(t[k][0, :, 0].astype(np.complex128)) ** 2
+        cdf = np.cumsum(p) / p.sum()
+        want = np.minimum(np.searchsorted(cdf, u[:, k], side="left"), d - 1)
+        near = np.min(np.abs(u[:, k][:, None] - cdf[None, :-1]), axis=1) <= d * 1e-6
+        assert np.array_equal(g["outcomes"][~near, k], want[~near])
+
+
+def test_single_site_and_trivial_dims(mpsmod):
+    from tests.parity_util import compare
+    _say("single site M=1 d=4; d=1 sites")
+    a = synth.to_c64([synth.random_site(1, 0, 0, 1, 4, 1)])
+    g = _run(mpsmod, a, 500, seed=2, emit_n=500)
+    compare(a, 2, g)
+    dl = [2, 1, 3, 1, 2]
+    t = synth.to_c64(synth.random_mps(12, dl, synth.ramp_bonds(dl, 8)))
+    g = _run(mpsmod, t, 300, seed=2, emit_n=300)
+    assert np.all(g["outcomes"][:, 1] == 0) and np.all(g["outcomes"][:, 3] == 0)
+    compare(t, 2, g)
+
+
+def test_chunking_and_offset_bit_exact(mpsmod):
+    """Outcomes and logp depend only on the global sample index."""
+    _say("chunk/offset invariance M=16 d=4 chi=64 N=2000")
+    t = _chain(13, 16, 4, 64)
+    full = _run(mpsmod, t, 2000, seed=31)
+    chunked = _run(mpsmod, t, 2000, seed=31, n_chunk=300)
+    a = _run(mpsmod, t, 700, seed=31)
+    b = _run(mpsmod, t, 1300, seed=31, n_offset=700)
+    assert np.array_equal(full["outcomes"], chunked["outcomes"])
+    assert np.array_equal(full["logp"], chunked["logp"])
+    assert np.array_equal(full["outcomes"], np.vstack([a["outcomes"], b["outcomes"]]))
+    assert np.array_equal(full["logp"], np.concatenate([a["logp"], b["logp"]]))
+    again = _run(mpsmod, t, 2000, seed=31)
+    assert np.array_equal(full["outcomes"], again["outcomes"]) and np.array_equal(full["logp"], again["logp"])
+
+
+def test_flagged_samples(mpsmod):
+    """A zero site tensor stops every sample: MPS_ENUMERIC, -1 outcomes, -inf logp."""
+    _say("flagged samples: zero tensor at site 3")
+    t = _chain(14, 8, 3, 9)
+    t[3] = np.zeros_like(t[3])
+    g = _run(mpsmod, t, 400, seed=1)
+    assert g["status"] == mpsmod.MPS_ENUMERIC
+    assert g["stats"].flagged == 400
+    assert np.all(g["outcomes"][:, 3:] == -1) and np.all(g["outcomes"][:, :3] >= 0)
+    assert np.all(np.isneginf(g["logp"]))
+
+
+def test_empty_and_memory_cap(mpsmod):
+    _say("N=0 and max_device_bytes forcing small chunks")
+    t = _chain(15, 6, 4, 16)
+    from tests.parity_util import upload
+    dev = upload(t)
+    s = mpsmod.Sampler(0)
+    r = s.sample(dev, 0, 1)
+    assert r["status"] == 0 and r["outcomes"].shape == (0, 6)
+    s.close()
+    s = mpsmod.Sampler(0, max_device_bytes=64 * 1024)
+    r = s.sample(dev, 1500, 3)
+    assert s.stats.n_chunk < 1500
+    ref = _run(mpsmod, t, 1500, seed=3)
+    assert np.array_equal(r["outcomes"].cpu().numpy(), ref["outcomes"])
+    s.close()
+
+
+def test_brute_force_distribution_on_gpu(mpsmod):
+    """TV of 10^6 GPU samples against brute-force enumeration on a tiny chain."""
+    import oracle
+    _say("GPU TV vs brute force M=6 d=2 chi=4 N=1e6")
+    M, d, chi = 6, 2, 4
+    t128 = synth.random_mps(106, [d] * M, synth.ramp_bonds([d] * M, chi))
+    t = synth.to_c64(t128)
+    configs, p = oracle.brute_force(synth.promote(t))
+    g = _run(mpsmod, t, 10**6, seed=2024)
+    hist = np.bincount(oracle.config_index(g["outcomes"], [d] * M), minlength=len(p)) / 10**6
+    tv = 0.5 * np.abs(hist[oracle.config_index(configs, [d] * M)] - p).sum()
+    assert tv <= 5e-3, tv
