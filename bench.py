@@ -27,13 +27,34 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "site-samples/s at χ=1024,d=4; MFMA util; low-prec vs FP32 at 1e-3 prob err"
-PEAK_TFLOPS = {"fp32": 157.3}
-KERNEL_SRC = os.path.join(ROOT, "paper_2512_20064_amd", "csrc", "sweep_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "contract_f32_traffic.json")
+KERNEL_DIR = os.path.join(ROOT, "paper_2512_20064_amd", "csrc")
+# Per form: MFMA peak of its operand type (MI355X, dense), MFMA products per
+# algorithmic complex product, the contraction kernel and its source.
+FORMS = {
+    "fp32": {"peak": 157.3, "mfma_per_alg": 1, "kernel": "contract_f32_kernel", "src": "contract_f32.hip",
+             "dtype": "f32"},
+    "bf16x3": {"peak": 2516.6, "mfma_per_alg": 3, "kernel": "contract_lp_kernel<bf16,3>", "src": "contract_lp.hip",
+               "dtype": "bf16x3"},
+    "fp16": {"peak": 2516.6, "mfma_per_alg": 1, "kernel": "contract_lp_kernel<f16,1>", "src": "contract_lp.hip",
+             "dtype": "f16"},
+}
 
 
-def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+def kernel_hash(form) -> str:
+    src = os.path.join(KERNEL_DIR, FORMS[form]["src"])
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def traffic_for(form, chunk):
+    """HBM bytes per launch of the contraction from committed counter runs,
+    or None if they were taken on another version of the kernel."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{form}.json")
+    if not os.path.exists(path):
+        return None
+    tr = json.load(open(path))
+    if tr.get("kernel_sha") != kernel_hash(form) or tr.get("chunk") != chunk:
+        return None
+    return tr.get("bytes_per_launch")
 
 
 def log(msg):
@@ -102,11 +123,15 @@ def main():
     ap.add_argument("--chi", type=int, default=1024)
     ap.add_argument("--pool", type=int, default=16)
     ap.add_argument("--chunk", type=int, default=65536)
-    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--precision", default="fp32", choices=sorted(FORMS))
+    ap.add_argument("--beside", default="", help="comma-separated forms also timed (e.g. fp32)")
+    ap.add_argument("--beside-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-samples", type=int, default=256)
-    ap.add_argument("--cpu-sites", type=int, default=96)
+    ap.add_argument("--cpu-samples", type=int, default=1024)
+    ap.add_argument("--cpu-sites", type=int, default=512)
     ap.add_argument("--no-profile", action="store_true", help="do not event-time each launch")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run one plain device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -127,50 +152,70 @@ def main():
     seed = 1003
     log(f"uploaded {M} sites, {sum(t.numel() * 8 for t in dev) / 2**30:.1f} GiB")
 
-    sampler = mps.Sampler(0, n_chunk=args.chunk, profile=not args.no_profile)
-    stream = torch.cuda.current_stream()
-    step = 0
-
-    def one_step():
-        nonlocal step
-        r = sampler.sample(dev, args.chunk, seed, n_offset=step * args.chunk, want_logp=True)
-        step += 1
-        return r
-
-    for w in range(args.warmup):
-        one_step()
+    if args.copy_calibration:
+        src = torch.empty(args.copy_calibration * 2**20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1)
         torch.cuda.synchronize()
-        log(f"warmup step {w} done")
-    torch.cuda.synchronize()
-    c_ms = m_ms = c_fl = 0.0
-    c_n = 0
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        one_step()
-        st = sampler.stats
-        c_ms += st.contract_ms
-        m_ms += st.measure_ms
-        c_fl += st.contract_flops
-        c_n += st.contract_launches
-        log(f"timed step {s} done")
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    site_samples = args.chunk * M * args.steps
-    value = site_samples / dt
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"copy calibration: {args.copy_calibration} MiB device-to-device copy")
 
-    roof = None
-    if not args.no_profile and c_ms > 0:
-        achieved = (c_fl / c_n) / (c_ms / c_n * 1e-3) / 1e12
-        peak = PEAK_TFLOPS[args.precision]
-        traffic = None
-        if os.path.exists(TRAFFIC_FILE):
-            tr = json.load(open(TRAFFIC_FILE))
-            if tr.get("kernel_sha") == kernel_hash() and tr.get("chunk") == args.chunk:
-                traffic = tr.get("bytes_per_launch")
-        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": traffic,
-                "kernel": "contract_f32", "avg_launch_ms": round(c_ms / c_n, 4),
-                "launches": c_n, "measure_ms_share": round(m_ms / max(c_ms + m_ms, 1e-9), 4)}
+    def run_form(form, steps, warmup):
+        sampler = mps.Sampler(0, n_chunk=args.chunk, profile=not args.no_profile, precision=form)
+        step = [0]
+
+        def one_step():
+            r = sampler.sample(dev, args.chunk, seed, n_offset=step[0] * args.chunk, want_logp=True)
+            step[0] += 1
+            return r
+
+        for w in range(warmup):
+            one_step()
+            torch.cuda.synchronize()
+            log(f"{form} warmup step {w} done")
+        torch.cuda.synchronize()
+        c_ms = m_ms = p_ms = c_fl = 0.0
+        c_n = 0
+        t0 = time.perf_counter()
+        for s_ in range(steps):
+            one_step()
+            st = sampler.stats
+            c_ms += st.contract_ms
+            m_ms += st.measure_ms
+            p_ms += st.pack_ms
+            c_fl += st.contract_flops
+            c_n += st.contract_launches
+            log(f"{form} timed step {s_} done")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        sampler.close()
+        out = {"value": args.chunk * M * steps / dt, "ms_per_step": dt / steps * 1e3, "dt": dt}
+        if not args.no_profile and c_ms > 0:
+            f = FORMS[form]
+            alg = (c_fl / c_n) / (c_ms / c_n * 1e-3) / 1e12
+            achieved = alg * f["mfma_per_alg"]
+            out["roofline"] = {
+                "bound": "mfma", "achieved": round(achieved, 2), "peak": f["peak"], "unit": "TFLOP/s",
+                "frac": round(achieved / f["peak"], 4), "traffic": traffic_for(form, args.chunk),
+                "kernel": f["kernel"], "algorithmic_tflops": round(alg, 2),
+                "mfma_products_per_complex_product": f["mfma_per_alg"],
+                "avg_launch_ms": round(c_ms / c_n, 4), "launches": c_n,
+                "time_share": {"contract": round(c_ms * 1e-3 / dt, 4), "measure": round(m_ms * 1e-3 / dt, 4),
+                               "pack": round(p_ms * 1e-3 / dt, 4)},
+            }
+        return out
+
+    main_res = run_form(args.precision, args.steps, args.warmup)
+    value, dt = main_res["value"], main_res["dt"]
+    roof = main_res.get("roofline")
+    beside = {}
+    for form in [f for f in args.beside.split(",") if f and f != args.precision]:
+        r = run_form(form, args.beside_steps, 0 if args.beside_steps == 0 else 1)
+        beside[form] = {"value": round(r["value"], 1), "ms_per_step": round(r["ms_per_step"], 2),
+                        "steps": args.beside_steps,
+                        "frac": r.get("roofline", {}).get("frac")}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -180,12 +225,16 @@ def main():
     rec = {
         "metric": METRIC, "value": round(value, 1), "unit": "site-samples/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 2),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": FORMS[args.precision]["dtype"],
         "data": "synthetic",
         "config": {"workload": wname, "sites": M, "d": 4, "chi": int(max(chi)), "samples_per_step": args.chunk,
                    "precision": args.precision, "tensor_bytes": int(sum(t.numel() * 8 for t in dev))},
         "roofline": roof, "cpu_baseline": cpu,
     }
+    if beside:
+        rec["beside"] = beside
+        if "fp32" in beside:
+            rec["speedup_vs_fp32"] = round(value / beside["fp32"]["value"], 3)
     print(json.dumps(rec), flush=True)
 
 

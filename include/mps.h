@@ -47,9 +47,16 @@ enum {
   MPS_ENUMERIC = -5  /* some samples met S <= 0 or a non-finite S; see below   */
 };
 
-/* Arithmetic of the contraction. */
+/* Arithmetic of the contraction (Section 3.3.1, mixed precision).  Every form
+ * accumulates in FP32; branch weights, normalisation, CDF, draw and logp are
+ * FP64 in all forms. */
 enum {
-  MPS_FP32 = 0       /* FP32 operands, FP32 MFMA accumulate (v_mfma_f32_32x32x2f32) */
+  MPS_FP32 = 0,      /* FP32 operands on v_mfma_f32_32x32x2f32                   */
+  MPS_BF16X3 = 1,    /* split precision: x = hi + lo (bf16 each) for the left
+                        vectors and the site tensor; W = Lh*Ah + Lh*Al + Ll*Ah on
+                        v_mfma_f32_32x32x16_bf16                                   */
+  MPS_FP16 = 2       /* one fp16 product on v_mfma_f32_32x32x16_f16, left vectors
+                        renormalised per sample (entries within [-1, 1])           */
 };
 
 /* Element type of the site tensors. */
@@ -60,7 +67,7 @@ enum {
 typedef struct mps_ctx* mps_handle;
 
 typedef struct {
-  int32_t precision;        /* MPS_FP32                                          */
+  int32_t precision;        /* MPS_FP32, MPS_BF16X3 or MPS_FP16                   */
   int32_t profile;          /* 1: time every kernel launch with HIP events        */
   int64_t n_chunk;          /* samples per pass over the chain; 0 = planner picks */
   int64_t max_device_bytes; /* cap on scratch bytes; 0 = no cap                  */
@@ -82,8 +89,10 @@ typedef struct {
 typedef struct {
   int64_t contract_launches;  /* contraction kernels launched by the last call     */
   int64_t measure_launches;   /* measurement kernels launched by the last call     */
+  int64_t pack_launches;      /* site-tensor packing kernels (16-bit forms)         */
   double contract_ms;         /* summed event time of those launches (profile=1)    */
   double measure_ms;
+  double pack_ms;
   double contract_flops;      /* algorithmic flops: 8 * rows * chi_l * d * chi_r summed */
   double measure_bytes;       /* algorithmic bytes of the measurement launches      */
   int64_t n_chunk;            /* chunk size the last call used                      */

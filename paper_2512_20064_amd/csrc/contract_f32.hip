@@ -1,14 +1,13 @@
-// HIP kernels of the MPS sampling sweep for gfx950 (MI355X).
+// FP32 contraction of the MPS sampling sweep for gfx950 (MI355X).
 //
 // One site of the sweep for a chunk of `rows` samples is two launches:
 //
-//   contract_f32  W = L * A_k on MFMA (an N x chi_l by chi_l x d*chi_r complex
+//   contract      W = L * A_k on MFMA (an N x chi_l by chi_l x d*chi_r complex
 //                 GEMM, Section 2.2 step 2), with the epilogue writing W and
-//                 the partial branch weights sum_r |W[n,i,r]|^2 of its tile;
-//   measure       per sample: branch weights in FP64, normalise, CDF, draw by
-//                 inverse CDF from the counter-based uniform, log-probability,
-//                 gather of the chosen branch and renormalisation
-//                 (Section 3.3.1, Algorithm 1).
+//                 the partial branch weights sum_r |W[n,i,r]|^2 of its tile
+//                 (this file: FP32; contract_lp.hip: 16-bit operands);
+//   measure       per sample: branch weights in FP64, normalise, CDF, draw,
+//                 log-probability, gather and renormalise (measure.hip).
 //
 // Complex arithmetic on real MFMA: with L stored as interleaved (re, im)
 // pairs, a complex product W = L A is the real product of L (rows x 2K) with
@@ -48,8 +47,17 @@ constexpr int STAGE = LFL + AFL;
 constexpr int LLOADS = BM * BK / NTHR;
 constexpr int ALOADS = BK * BNC / NTHR;
 static_assert(BM * BK % NTHR == 0 && BK * BNC % NTHR == 0, "tile loads must divide evenly");
-static_assert(BM == 128 && BNC == 128, "wave layout below assumes a 128 x 128 tile");
+static_assert(BM == 128 && BNC == 64, "wave layout below assumes a 128 x 64 (complex) tile");
 
+// Four waves in a 2 x 2 grid; each owns 64 rows x 32 complex columns, i.e.
+// 2 x 2 output blocks of 32 rows x 16 complex (32 real) columns.
+//
+// Accumulation is two-level: each K tile (BK complex = 2*BK real terms) is
+// summed into fresh MFMA accumulators, which are then added to running FP32
+// totals.  Summing 2K real products in one FP32 chain gives a relative error
+// of order u*sqrt(K) per output; blocking it into K/BK partial sums cuts that
+// by about sqrt(BK), which matters because the rounding error of the left
+// vector is carried from site to site.
 __global__ __launch_bounds__(NTHR, 2) void contract_f32_kernel(ContractArgs a, int tiles_m, int tiles_n,
                                                               int per_xcd) {
   __shared__ float lds[2 * STAGE];
@@ -75,26 +83,45 @@ __global__ __launch_bounds__(NTHR, 2) void contract_f32_kernel(ContractArgs a, i
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wr = (wave >> 1) * 64;  // wave's first row in the tile
-  const int wc = (wave & 1) * 64;   // wave's first complex column in the tile
+  const int wc = (wave & 1) * 32;   // wave's first complex column in the tile
   const int half = lane >> 5;
   const int j = lane & 31;
 
   float2 lreg[LLOADS];
   float2 areg[ALOADS];
+  // Interior tiles (all rows, K and columns in range: every tile of a
+  // plateau site) load without masks; edge tiles zero what is out of range.
+  const bool rows_full = m0 + BM <= a.rows;
+  const bool cols_full = c0 + BNC <= a.chi_r;
   auto gload = [&](int k0) {
+    if (rows_full && cols_full && k0 + BK <= a.K) {
 #pragma unroll
-    for (int it = 0; it < LLOADS; ++it) {
-      const int idx = it * NTHR + tid;
-      const int r = idx / BK, c = idx % BK;
-      const int gr = m0 + r, gk = k0 + c;
-      lreg[it] = (gr < a.rows && gk < a.K) ? a.L[(size_t)gr * a.K + gk] : make_float2(0.f, 0.f);
-    }
+      for (int it = 0; it < LLOADS; ++it) {
+        const int idx = it * NTHR + tid;
+        const int r = idx / BK, c = idx % BK;
+        lreg[it] = a.L[(size_t)(m0 + r) * a.K + k0 + c];
+      }
 #pragma unroll
-    for (int it = 0; it < ALOADS; ++it) {
-      const int idx = it * NTHR + tid;
-      const int r = idx / BNC, c = idx % BNC;
-      const int gk = k0 + r;
-      areg[it] = (gk < a.K && c0 + c < a.chi_r) ? Ab[(size_t)gk * ncols + c] : make_float2(0.f, 0.f);
+      for (int it = 0; it < ALOADS; ++it) {
+        const int idx = it * NTHR + tid;
+        const int r = idx / BNC, c = idx % BNC;
+        areg[it] = Ab[(size_t)(k0 + r) * ncols + c];
+      }
+    } else {
+#pragma unroll
+      for (int it = 0; it < LLOADS; ++it) {
+        const int idx = it * NTHR + tid;
+        const int r = idx / BK, c = idx % BK;
+        const int gr = m0 + r, gk = k0 + c;
+        lreg[it] = (gr < a.rows && gk < a.K) ? a.L[(size_t)gr * a.K + gk] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int it = 0; it < ALOADS; ++it) {
+        const int idx = it * NTHR + tid;
+        const int r = idx / BNC, c = idx % BNC;
+        const int gk = k0 + r;
+        areg[it] = (gk < a.K && c0 + c < a.chi_r) ? Ab[(size_t)gk * ncols + c] : make_float2(0.f, 0.f);
+      }
     }
   };
   auto sstore = [&](float* st) {
@@ -114,13 +141,12 @@ __global__ __launch_bounds__(NTHR, 2) void contract_f32_kernel(ContractArgs a, i
     }
   };
 
-  floatx16 acc[2][4];
+  floatx16 tot[2][2], blk[2][2];
+  const floatx16 zero = {};
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[rb][cb][v] = 0.f;
+    for (int cb = 0; cb < 2; ++cb) tot[rb][cb] = zero;
 
   // Lane roles in v_mfma_f32_32x32x2f32: A lane (j, half) holds A[row j][k = half],
   // B lane (j, half) holds B[k = half][col j].
@@ -140,16 +166,20 @@ __global__ __launch_bounds__(NTHR, 2) void contract_f32_kernel(ContractArgs a, i
     for (int kk = 0; kk < BK; ++kk) {
       const float a0 = st[kk * LP + aoff];
       const float a1 = st[kk * LP + aoff + 32];
-      float bv[4];
+      float bv[2];
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb)
+      for (int cb = 0; cb < 2; ++cb)
         bv[cb] = __uint_as_float(__float_as_uint(as[kk * AP + boff + cb * 32]) ^ sgn);
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
-        acc[0][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bv[cb], acc[0][cb], 0, 0, 0);
-        acc[1][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bv[cb], acc[1][cb], 0, 0, 0);
+      for (int cb = 0; cb < 2; ++cb) {
+        blk[0][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bv[cb], kk ? blk[0][cb] : zero, 0, 0, 0);
+        blk[1][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bv[cb], kk ? blk[1][cb] : zero, 0, 0, 0);
       }
     }
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) tot[rb][cb] += blk[rb][cb];
     if (kt + 1 < nkt) sstore(lds + ((kt + 1) & 1) * STAGE);
     __syncthreads();
   }
@@ -161,14 +191,14 @@ __global__ __launch_bounds__(NTHR, 2) void contract_f32_kernel(ContractArgs a, i
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb) {
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
+    for (int cb = 0; cb < 2; ++cb) {
       const int colc = c0 + wc + cb * 16 + (j >> 1);
       const size_t fcol = 2 * ((size_t)branch * a.chi_r + c0 + wc + cb * 16) + j;
       if (colc < a.chi_r) {
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const int gr = m0 + wr + rb * 32 + (v >> 2) * 8 + half * 4 + (v & 3);
-          if (gr < a.rows) Wf[(size_t)gr * wpitch + fcol] = acc[rb][cb][v];
+          if (gr < a.rows) Wf[(size_t)gr * wpitch + fcol] = tot[rb][cb][v];
         }
       }
     }
@@ -185,7 +215,7 @@ __global__ __launch_bounds__(NTHR, 2) void contract_f32_kernel(ContractArgs a, i
     for (int v = 0; v < 16; ++v) {
       float s = 0.f;
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) s += acc[rb][cb][v] * acc[rb][cb][v];
+      for (int cb = 0; cb < 2; ++cb) s += tot[rb][cb][v] * tot[rb][cb][v];
 #pragma unroll
       for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off, 32);
       if (j == 0) red[(wave & 1) * BM + wr + rb * 32 + (v >> 2) * 8 + half * 4 + (v & 3)] = s;
@@ -198,131 +228,7 @@ __global__ __launch_bounds__(NTHR, 2) void contract_f32_kernel(ContractArgs a, i
   }
 }
 
-// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): first output word for
-// counter (c0, c1, 0, 0) and key (k0, k1).
-__device__ inline uint64_t philox_word0(uint64_t c0, uint64_t c1, uint64_t k0, uint64_t k1) {
-  constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-  constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
-  uint64_t x0 = c0, x1 = c1, x2 = 0, x3 = 0;
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r) {
-      k0 += W0;
-      k1 += W1;
-    }
-    const uint64_t hi0 = __umul64hi(M0, x0), lo0 = M0 * x0;
-    const uint64_t hi1 = __umul64hi(M1, x2), lo1 = M1 * x2;
-    const uint64_t y0 = hi1 ^ x1 ^ k0, y2 = hi0 ^ x3 ^ k1;
-    x0 = y0;
-    x1 = lo1;
-    x2 = y2;
-    x3 = lo0;
-  }
-  return x0;
-}
-
-constexpr int DMAX = 16;
-
-// One wave per sample.  All lanes evaluate the scalar part redundantly (it is
-// a few dozen FP64 operations); lane 0 writes the per-sample results, and the
-// wave gathers the chosen branch.
-__global__ __launch_bounds__(256) void measure_kernel(MeasureArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= a.rows) return;
-  const int d = a.d, T = a.T;
-  const float* qp = a.qpart + (size_t)row * (d * T);
-
-  double q[DMAX], P[DMAX];
-  double acc = 0.0;
-#pragma unroll
-  for (int i = 0; i < DMAX; ++i) {
-    double qi = 0.0;
-    if (i < d)
-      for (int t = 0; t < T; ++t) qi += (double)qp[i * T + t];
-    q[i] = qi;
-    acc += qi;  // left-to-right prefix sums
-    P[i] = acc;
-  }
-  double S = 0.0;
-#pragma unroll
-  for (int i = 0; i < DMAX; ++i)
-    if (i == d - 1) S = P[i];
-
-  const double lp_prev = a.logp[row];
-  const bool alive = !(lp_prev == -INFINITY);
-  bool ok = alive && isfinite(S) && S > 0.0;
-
-  const uint64_t n = (uint64_t)(a.n0 + row);
-  const uint64_t x = philox_word0(n, (uint64_t)a.site, a.seed, a.mps_id);
-  const double u = ((double)(x >> 12) + 0.5) * 0x1p-52;
-
-  int s = 0;
-#pragma unroll
-  for (int i = 0; i < DMAX; ++i)
-    if (i < d && u > P[i] / S) ++s;  // C_i = P_i / S;  C_{d-1} == 1
-  if (s > d - 1) s = d - 1;
-  double qs = 0.0;
-#pragma unroll
-  for (int i = 0; i < DMAX; ++i)
-    if (i == s) qs = q[i];
-  ok = ok && qs > 0.0;
-  if (!ok) s = 0;
-
-  if (lane == 0) {
-    a.outcomes[(size_t)row * a.M + a.site] = ok ? s : -1;
-    a.logp[row] = ok ? lp_prev + (log(qs) - log(S)) : -INFINITY;
-    if (alive && !ok) atomicAdd(a.nflag, 1);
-    if (row < a.emit_rows) {
-      if (a.emit_u) a.emit_u[(size_t)row * a.M + a.site] = u;
-      if (a.emit_probs) {
-        double* ep = a.emit_probs + ((size_t)row * a.M + a.site) * a.emit_dmax;
-#pragma unroll
-        for (int i = 0; i < DMAX; ++i)
-          if (i < d && i < a.emit_dmax) ep[i] = ok ? q[i] / S : NAN;
-      }
-    }
-  }
-
-  const float2* src = a.W + (size_t)row * d * a.chi_r + (size_t)s * a.chi_r;
-  float2* dst = a.Lout + (size_t)row * a.chi_r;
-  if (ok) {
-    const float scale = (float)(1.0 / sqrt(qs));
-    for (int r = lane; r < a.chi_r; r += 64) {
-      const float2 w = src[r];
-      dst[r] = make_float2(w.x * scale, w.y * scale);
-    }
-  } else {
-    for (int r = lane; r < a.chi_r; r += 64) dst[r] = make_float2(0.f, 0.f);
-  }
-}
-
-__global__ void init_kernel(float2* L, double* logp, int rows) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < rows) {
-    L[i] = make_float2(1.f, 0.f);  // chi_0 = 1: the open left end
-    logp[i] = 0.0;
-  }
-}
-
-__global__ void zero_int_kernel(int* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0;
-}
-
 }  // namespace
-
-hipError_t launch_init(float2* L, double* logp, int rows, hipStream_t s) {
-  if (rows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(init_kernel, dim3((rows + 255) / 256), dim3(256), 0, s, L, logp, rows);
-  return hipGetLastError();
-}
-
-hipError_t launch_zero_int(int* p, int n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(zero_int_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
-  return hipGetLastError();
-}
 
 hipError_t launch_contract_f32(const ContractArgs& a, hipStream_t s) {
   const int tiles_m = (a.rows + BM - 1) / BM;
@@ -331,12 +237,6 @@ hipError_t launch_contract_f32(const ContractArgs& a, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   const int per_xcd = (int)((ntiles + 7) / 8);
   hipLaunchKernelGGL(contract_f32_kernel, dim3(per_xcd * 8), dim3(NTHR), 0, s, a, tiles_m, tiles_n, per_xcd);
-  return hipGetLastError();
-}
-
-hipError_t launch_measure(const MeasureArgs& a, hipStream_t s) {
-  if (a.rows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(measure_kernel, dim3((a.rows + 3) / 4), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

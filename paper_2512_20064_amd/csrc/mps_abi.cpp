@@ -5,11 +5,13 @@
 // Sweep structure (Section 3.1, Eq. 2-3): the N samples of a call are cut
 // into chunks (the paper's macro batches); each chunk walks all M sites in
 // order (the dependency between sites is strict, Section 2.2), one
-// contraction and one measurement launch per site, all on one stream.  Work
-// inside a site is data-parallel over samples and columns.  Scratch per
-// chunk holds one left-vector buffer (the measurement overwrites the
-// contraction's input in place of a second buffer: the contraction has
-// finished reading it), the site output W and the partial branch weights.
+// contraction and one measurement launch per site (plus, for the 16-bit
+// forms, one packing launch that converts the site tensor into the operand
+// format), all on one stream.  Work inside a site is data-parallel over
+// samples and columns.  Scratch per chunk holds one left-vector buffer (the
+// measurement overwrites the contraction's input in place of a second
+// buffer: the contraction has finished reading it), the site output W and
+// the partial branch weights.
 
 #include "../../include/mps.h"
 #include "sweep.h"
@@ -47,7 +49,8 @@ constexpr int kMaxChi = 65536;
 constexpr int64_t kDefaultChunk = 65536;
 
 int check_options(const mps_options* o) {
-  if (o->precision != MPS_FP32) return fail(MPS_EINVAL, "unknown precision %d", o->precision);
+  if (o->precision != MPS_FP32 && o->precision != MPS_BF16X3 && o->precision != MPS_FP16)
+    return fail(MPS_EINVAL, "unknown precision %d", o->precision);
   if (o->n_chunk < 0) return fail(MPS_EINVAL, "n_chunk < 0");
   if (o->max_device_bytes < 0) return fail(MPS_EINVAL, "max_device_bytes < 0");
   if (o->emit_n < 0) return fail(MPS_EINVAL, "emit_n < 0");
@@ -58,26 +61,48 @@ int check_options(const mps_options* o) {
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Scratch layout for a chunk of `rows` samples.
-struct Layout {
-  size_t L, W, qpart, logp, nflag, total;
+//   FP32 path:  L [rows][chimax] complex, W, qpart, logp, flag counter.
+//   16-bit path: Lh/Ll [rows_alloc][kpmax] 16-bit (rows_alloc a multiple of
+//   the 256-row tile, so the contraction reads whole tiles), the packed site
+//   tensor Bh/Bl, W, qpart, logp, flag counter.
+struct Shape {
+  int chimax = 1;
+  int64_t wmax = 1;      // max d_k * chi_{k+1} (complex)
+  int64_t qtmax = 1;     // max partial weights per sample
+  int64_t kpmax = 64;    // max padded K of the 16-bit left vectors
+  int64_t bmax = 1;      // max packed site-tensor elements
 };
 
-Layout layout_for(int64_t rows, int chimax, int64_t wmax, int64_t qtmax) {
+struct Layout {
+  size_t L = 0, Lh = 0, Ll = 0, Bh = 0, Bl = 0, W = 0, qpart = 0, logp = 0, nflag = 0, total = 0;
+};
+
+Layout layout_for(int64_t rows, const Shape& sh, int precision) {
   Layout l;
   size_t off = 0;
-  l.L = off;
-  off += align_up((size_t)rows * chimax * sizeof(float2));
-  l.W = off;
-  off += align_up((size_t)rows * wmax * sizeof(float2));
-  l.qpart = off;
-  off += align_up((size_t)rows * qtmax * sizeof(float));
-  l.logp = off;
-  off += align_up((size_t)rows * sizeof(double));
-  l.nflag = off;
-  off += align_up(sizeof(int));
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += align_up(bytes);
+    return at;
+  };
+  if (precision == MPS_FP32) {
+    l.L = take((size_t)rows * sh.chimax * sizeof(float2));
+  } else {
+    const size_t ra = (size_t)((rows + mps::kLpBM - 1) / mps::kLpBM * mps::kLpBM);
+    l.Lh = take(ra * sh.kpmax * 2);
+    if (precision == MPS_BF16X3) l.Ll = take(ra * sh.kpmax * 2);
+    l.Bh = take((size_t)sh.bmax * 2);
+    if (precision == MPS_BF16X3) l.Bl = take((size_t)sh.bmax * 2);
+  }
+  l.W = take((size_t)rows * sh.wmax * sizeof(float2));
+  l.qpart = take((size_t)rows * sh.qtmax * sizeof(float));
+  l.logp = take((size_t)rows * sizeof(double));
+  l.nflag = take(sizeof(int));
   l.total = off;
   return l;
 }
+
+int lp_form(int precision) { return precision == MPS_BF16X3 ? mps::kBf16x3 : mps::kFp16; }
 
 }  // namespace
 
@@ -162,11 +187,13 @@ int mps_sample(mps_handle h, const void* const* tensors, int32_t dtype, const in
   if (N > INT64_MAX - n_offset) return fail(MPS_EINVAL, "n_offset + N overflows");
   if (dtype != MPS_C64) return fail(MPS_EINVAL, "unknown dtype %d", dtype);
   if (chi[0] != 1) return fail(MPS_EINVAL, "chi[0] = %d, must be 1 (open left end)", chi[0]);
-  int chimax = 1;
-  int64_t wmax = 1, qtmax = 1;
+  const mps_options& o = h->opt;
+  const bool lowp = o.precision != MPS_FP32;
+  Shape sh;
   for (int k = 0; k <= M; ++k) {
     if (chi[k] < 1 || chi[k] > kMaxChi) return fail(MPS_EINVAL, "chi[%d] = %d out of [1, %d]", k, chi[k], kMaxChi);
-    chimax = std::max(chimax, chi[k]);
+    sh.chimax = std::max(sh.chimax, chi[k]);
+    sh.kpmax = std::max<int64_t>(sh.kpmax, mps::lp_pad_k(chi[k]));
   }
   for (int k = 0; k < M; ++k) {
     if (d[k] < 1 || d[k] > kMaxD) return fail(MPS_EINVAL, "d[%d] = %d out of [1, %d]", k, d[k], kMaxD);
@@ -174,8 +201,14 @@ int mps_sample(mps_handle h, const void* const* tensors, int32_t dtype, const in
       return fail(MPS_EINVAL, "chi[%d] = %d > d[%d]*chi[%d] = %lld: no right-canonical tensor", k, chi[k], k, k + 1,
                   (long long)d[k] * chi[k + 1]);
     if (!tensors[k]) return fail(MPS_EINVAL, "tensors[%d] is NULL", k);
-    wmax = std::max<int64_t>(wmax, (int64_t)d[k] * chi[k + 1]);
-    qtmax = std::max<int64_t>(qtmax, (int64_t)d[k] * mps::col_tiles(chi[k + 1]));
+    sh.wmax = std::max<int64_t>(sh.wmax, (int64_t)d[k] * chi[k + 1]);
+    if (lowp) {
+      const int CP = mps::lp_pad_cols(chi[k + 1]);
+      sh.qtmax = std::max<int64_t>(sh.qtmax, (int64_t)d[k] * (CP / mps::kLpBNC));
+      sh.bmax = std::max<int64_t>(sh.bmax, (int64_t)d[k] * CP * 2 * mps::lp_pad_k(chi[k]));
+    } else {
+      sh.qtmax = std::max<int64_t>(sh.qtmax, (int64_t)d[k] * mps::col_tiles(chi[k + 1]));
+    }
   }
   if (N == 0) {
     h->st = mps_stats{};
@@ -183,7 +216,6 @@ int mps_sample(mps_handle h, const void* const* tensors, int32_t dtype, const in
     return MPS_OK;
   }
   if (!outcomes) return fail(MPS_EINVAL, "outcomes is NULL");
-  const mps_options& o = h->opt;
   if (o.emit_n > 0 && o.emit_probs && o.emit_dmax < 1) return fail(MPS_EINVAL, "emit_dmax < 1");
 
   // ---- plan the chunk ----
@@ -191,13 +223,13 @@ int mps_sample(mps_handle h, const void* const* tensors, int32_t dtype, const in
   nc = std::min<int64_t>(nc, N);
   nc = std::min<int64_t>(nc, (int64_t)1 << 30);
   if (o.max_device_bytes > 0) {
-    Layout one = layout_for(1, chimax, wmax, qtmax);
+    const Layout one = layout_for(1, sh, o.precision);
     if ((int64_t)one.total > o.max_device_bytes)
       return fail(MPS_ENOMEM, "scratch for one sample (%zu B) exceeds max_device_bytes (%lld)", one.total,
                   (long long)o.max_device_bytes);
-    while (nc > 1 && (int64_t)layout_for(nc, chimax, wmax, qtmax).total > o.max_device_bytes) nc = (nc + 1) / 2;
+    while (nc > 1 && (int64_t)layout_for(nc, sh, o.precision).total > o.max_device_bytes) nc = (nc + 1) / 2;
   }
-  const Layout lay = layout_for(nc, chimax, wmax, qtmax);
+  const Layout lay = layout_for(nc, sh, o.precision);
 
   // ---- device ----
   int ndev = 0;
@@ -225,18 +257,27 @@ int mps_sample(mps_handle h, const void* const* tensors, int32_t dtype, const in
   }
   char* base = (char*)h->scratch;
   float2* Lbuf = (float2*)(base + lay.L);
+  void* Lh = base + lay.Lh;
+  void* Ll = lay.Ll ? (void*)(base + lay.Ll) : nullptr;
+  void* Bh = base + lay.Bh;
+  void* Bl = lay.Bl ? (void*)(base + lay.Bl) : nullptr;
   float2* Wbuf = (float2*)(base + lay.W);
   float* qbuf = (float*)(base + lay.qpart);
   double* lpbuf = (double*)(base + lay.logp);
   int* nflag = (int*)(base + lay.nflag);
+  const int form = lowp ? lp_form(o.precision) : 0;
 
+  // events per site: pack begin/end, contract begin/end, measure begin/end
   const bool prof = o.profile != 0;
-  const size_t nev = prof ? (size_t)4 * M : 0;
+  const size_t nev = prof ? (size_t)6 * M : 0;
   while (h->events.size() < nev) {
     hipEvent_t ev;
     if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_fail(e, "hipEventCreate");
     h->events.push_back(ev);
   }
+  auto mark = [&](int k, int which) -> hipError_t {
+    return prof ? hipEventRecord(h->events[6 * k + which], stream) : hipSuccess;
+  };
 
   mps_stats st{};
   st.n_chunk = nc;
@@ -247,34 +288,49 @@ int mps_sample(mps_handle h, const void* const* tensors, int32_t dtype, const in
   for (int64_t c0 = 0; c0 < N; c0 += nc) {
     const int rows = (int)std::min<int64_t>(nc, N - c0);
     double* lp = logp ? logp + c0 : lpbuf;
-    if ((e = mps::launch_init(Lbuf, lp, rows, stream)) != hipSuccess) return hip_fail(e, "init kernel");
+    if (lowp)
+      e = mps::launch_init_lp(form, Lh, Ll, mps::lp_pad_k(chi[0]), lp, rows, stream);
+    else
+      e = mps::launch_init(Lbuf, lp, rows, stream);
+    if (e != hipSuccess) return hip_fail(e, "init kernel");
     int64_t emit_rows = 0;
     if (o.emit_n > c0) emit_rows = std::min<int64_t>(o.emit_n - c0, rows);
     for (int k = 0; k < M; ++k) {
       const int K = chi[k], dk = d[k], chr = chi[k + 1];
-      mps::ContractArgs ca;
-      ca.L = Lbuf;
-      ca.A = (const float2*)tensors[k];
-      ca.W = Wbuf;
-      ca.qpart = qbuf;
-      ca.rows = rows;
-      ca.K = K;
-      ca.d = dk;
-      ca.chi_r = chr;
-      if (prof && (e = hipEventRecord(h->events[4 * k], stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-      if ((e = mps::launch_contract_f32(ca, stream)) != hipSuccess) return hip_fail(e, "contraction launch");
-      if (prof && (e = hipEventRecord(h->events[4 * k + 1], stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+      int T = 0;
+      if (lowp) {
+        const int CP = mps::lp_pad_cols(chr), Kp = mps::lp_pad_k(K);
+        T = CP / mps::kLpBNC;
+        mps::PackArgs pa{(const float2*)tensors[k], Bh, Bl, K, dk, chr, CP, Kp};
+        if ((e = mark(k, 0)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        if ((e = mps::launch_pack_lp(form, pa, stream)) != hipSuccess) return hip_fail(e, "pack launch");
+        if ((e = mark(k, 1)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        st.pack_launches++;
+        mps::ContractLpArgs ca{Lh, Ll, Bh, Bl, Wbuf, qbuf, rows, Kp, dk, chr, CP};
+        if ((e = mark(k, 2)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        if ((e = mps::launch_contract_lp(form, ca, stream)) != hipSuccess) return hip_fail(e, "contraction launch");
+        if ((e = mark(k, 3)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+      } else {
+        T = mps::col_tiles(chr);
+        mps::ContractArgs ca{Lbuf, (const float2*)tensors[k], Wbuf, qbuf, rows, K, dk, chr};
+        if ((e = mark(k, 2)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        if ((e = mps::launch_contract_f32(ca, stream)) != hipSuccess) return hip_fail(e, "contraction launch");
+        if ((e = mark(k, 3)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+      }
       st.contract_launches++;
       st.contract_flops += 8.0 * rows * (double)K * dk * chr;
 
-      mps::MeasureArgs ma;
+      mps::MeasureArgs ma{};
       ma.W = Wbuf;
       ma.qpart = qbuf;
       ma.Lout = Lbuf;
+      ma.Lh = Lh;
+      ma.Ll = Ll;
+      ma.ld_out = mps::lp_pad_k(chr);
       ma.rows = rows;
       ma.d = dk;
       ma.chi_r = chr;
-      ma.T = mps::col_tiles(chr);
+      ma.T = T;
       ma.site = k;
       ma.M = M;
       ma.n0 = n_offset + c0;
@@ -287,26 +343,27 @@ int mps_sample(mps_handle h, const void* const* tensors, int32_t dtype, const in
       ma.emit_dmax = o.emit_dmax;
       ma.emit_probs = (emit_rows > 0 && o.emit_probs) ? o.emit_probs + (size_t)c0 * M * o.emit_dmax : nullptr;
       ma.emit_u = (emit_rows > 0 && o.emit_u) ? o.emit_u + (size_t)c0 * M : nullptr;
-      if (prof && (e = hipEventRecord(h->events[4 * k + 2], stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-      if ((e = mps::launch_measure(ma, stream)) != hipSuccess) return hip_fail(e, "measurement launch");
-      if (prof && (e = hipEventRecord(h->events[4 * k + 3], stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+      if ((e = mark(k, 4)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+      e = lowp ? mps::launch_measure_lp(form, ma, stream) : mps::launch_measure(ma, stream);
+      if (e != hipSuccess) return hip_fail(e, "measurement launch");
+      if ((e = mark(k, 5)) != hipSuccess) return hip_fail(e, "hipEventRecord");
       st.measure_launches++;
-      // qpart read + chosen branch read + new left vector write + outcome + logp read/write
-      st.measure_bytes += (double)rows * ((double)dk * ma.T * 4 + 2.0 * chr * 8 + 4 + 16);
-    }
-    if (!logp) {
-      // logp not requested: nothing to copy out
+      // partial weights read + chosen branch read + new left vector write + outcome + logp read/write
+      st.measure_bytes += (double)rows * ((double)dk * T * 4 + 2.0 * chr * 8 + 4 + 16);
     }
     if (prof) {
       if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
       for (int k = 0; k < M; ++k) {
-        float a = 0.f, b = 0.f;
-        if ((e = hipEventElapsedTime(&a, h->events[4 * k], h->events[4 * k + 1])) != hipSuccess)
+        float a = 0.f, b = 0.f, c = 0.f;
+        if (lowp && (e = hipEventElapsedTime(&c, h->events[6 * k], h->events[6 * k + 1])) != hipSuccess)
           return hip_fail(e, "hipEventElapsedTime");
-        if ((e = hipEventElapsedTime(&b, h->events[4 * k + 2], h->events[4 * k + 3])) != hipSuccess)
+        if ((e = hipEventElapsedTime(&a, h->events[6 * k + 2], h->events[6 * k + 3])) != hipSuccess)
+          return hip_fail(e, "hipEventElapsedTime");
+        if ((e = hipEventElapsedTime(&b, h->events[6 * k + 4], h->events[6 * k + 5])) != hipSuccess)
           return hip_fail(e, "hipEventElapsedTime");
         st.contract_ms += a;
         st.measure_ms += b;
+        st.pack_ms += c;
       }
     }
   }

@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmps.so")
 
 MPS_OK, MPS_EINVAL, MPS_ENOMEM, MPS_ENODEV, MPS_EHIP, MPS_ENUMERIC = 0, -1, -2, -3, -4, -5
-MPS_FP32 = 0
+MPS_FP32, MPS_BF16X3, MPS_FP16 = 0, 1, 2
+PRECISIONS = {"fp32": MPS_FP32, "bf16x3": MPS_BF16X3, "fp16": MPS_FP16}
 MPS_C64 = 0
 
 STATUS_NAMES = {0: "MPS_OK", -1: "MPS_EINVAL", -2: "MPS_ENOMEM", -3: "MPS_ENODEV",
@@ -46,8 +47,10 @@ class mps_stats(ctypes.Structure):
     _fields_ = [
         ("contract_launches", ctypes.c_int64),
         ("measure_launches", ctypes.c_int64),
+        ("pack_launches", ctypes.c_int64),
         ("contract_ms", ctypes.c_double),
         ("measure_ms", ctypes.c_double),
+        ("pack_ms", ctypes.c_double),
         ("contract_flops", ctypes.c_double),
         ("measure_bytes", ctypes.c_double),
         ("n_chunk", ctypes.c_int64),
@@ -155,7 +158,9 @@ class Sampler:
     """
 
     def __init__(self, device: int = 0, n_chunk: int = 0, profile: bool = False,
-                 max_device_bytes: int = 0, mps_id: int = 0, precision: int = MPS_FP32):
+                 max_device_bytes: int = 0, mps_id: int = 0, precision=MPS_FP32):
+        if isinstance(precision, str):
+            precision = PRECISIONS[precision]
         self.opt = mps_options_init()
         self.opt.n_chunk = n_chunk
         self.opt.profile = int(profile)

@@ -35,12 +35,13 @@ def upload(tensors_c64, device="cuda"):
     return out
 
 
-def compare(tensors_c64, seed, gpu, rows=None, n_offset=0, eps=EPS_FP32, mps_id=0):
+def compare(tensors_c64, seed, gpu, rows=None, n_offset=0, eps=EPS_FP32, mps_id=0, n_index=None):
     """Forced-prefix comparison of a GPU result dict with the oracle.
 
     gpu: dict with numpy 'outcomes' [N, M], 'logp' [N], optional 'probs'
     [E, M, dmax] and 'u' [E, M] for the first E rows.  rows: which rows to
-    check (default all).  Returns a report dict; raises AssertionError on a
+    check (default all); n_index: their global sample indices (default
+    n_offset + rows).  Returns a report dict; raises AssertionError on a
     violated bar.
     """
     outc = gpu["outcomes"]
@@ -49,7 +50,9 @@ def compare(tensors_c64, seed, gpu, rows=None, n_offset=0, eps=EPS_FP32, mps_id=
         rows = np.arange(N)
     rows = np.asarray(rows)
     t128 = synth.promote(tensors_c64)
-    f = oracle.forced_probs(t128, outc[rows], seed, mps_id=mps_id, n_index=n_offset + rows)
+    if n_index is None:
+        n_index = n_offset + rows
+    f = oracle.forced_probs(t128, outc[rows], seed, mps_id=mps_id, n_index=np.asarray(n_index))
     d = np.array([t.shape[1] for t in tensors_c64])
     rep = {"rows": int(len(rows)), "sites": int(M)}
 
@@ -68,6 +71,10 @@ def compare(tensors_c64, seed, gpu, rows=None, n_offset=0, eps=EPS_FP32, mps_id=
             rep["prob_err_max"] = float(err.max()) if err.size else 0.0
             rep["prob_err_mean"] = float(err.mean()) if err.size else 0.0
             rep["prob_err_p999"] = float(np.quantile(err, 0.999)) if err.size else 0.0
+            per_site = np.nanmax(np.where(valid, diff, np.nan), axis=(0, 2))
+            rep["prob_err_worst_site"] = int(np.nanargmax(per_site))
+            if per_site.size >= 8:  # growth along the chain: max error per eighth of the sites
+                rep["prob_err_by_eighth"] = [float(np.nanmax(c)) for c in np.array_split(per_site, 8)]
             assert not np.isnan(diff[valid]).any(), "NaN probability on the GPU"
             assert rep["prob_err_max"] <= eps, rep
 

@@ -27,10 +27,14 @@ def mpsmod():
     return mps
 
 
-def _run(mpsmod, tensors_c64, N, seed, n_offset=0, n_chunk=0, emit_n=0, profile=False):
+FORMS = ["fp32", "bf16x3", "fp16"]
+EPS = {"fp32": 1e-5, "bf16x3": 1e-3, "fp16": 1e-3}
+
+
+def _run(mpsmod, tensors_c64, N, seed, n_offset=0, n_chunk=0, emit_n=0, profile=False, precision="fp32"):
     from tests.parity_util import upload
     dev = upload(tensors_c64)
-    s = mpsmod.Sampler(0, n_chunk=n_chunk, profile=profile)
+    s = mpsmod.Sampler(0, n_chunk=n_chunk, profile=profile, precision=precision)
     r = s.sample(dev, N, seed, n_offset=n_offset, emit_n=emit_n)
     torch.cuda.synchronize()
     out = {"outcomes": r["outcomes"].cpu().numpy(), "logp": r["logp"].cpu().numpy(), "status": r["status"]}
@@ -48,50 +52,54 @@ def _chain(seed, M, d, chi_max):
     return synth.to_c64(synth.random_mps(seed, dl, chi))
 
 
-def test_small_chain_parity(mpsmod):
+@pytest.mark.parametrize("form", FORMS)
+def test_small_chain_parity(mpsmod, form):
     """M=32, d=4, chi=32 ramp, N=4096: every row, every site."""
     from tests.parity_util import compare
-    _say("small chain M=32 d=4 chi=32 N=4096")
+    _say(f"small chain M=32 d=4 chi=32 N=4096 {form}")
     t = _chain(1, 32, 4, 32)
-    g = _run(mpsmod, t, 4096, seed=1001, emit_n=4096)
+    g = _run(mpsmod, t, 4096, seed=1001, emit_n=4096, precision=form)
     assert g["status"] == 0
-    rep = compare(t, 1001, g)
+    rep = compare(t, 1001, g, eps=EPS[form])
     print(rep)
 
 
-def test_ragged_tiles_and_chunks(mpsmod):
+@pytest.mark.parametrize("form", FORMS)
+def test_ragged_tiles_and_chunks(mpsmod, form):
     """N not a multiple of the 128-row tile, chunk tail, chi_r not a multiple
     of the 128-column tile, odd bonds (d=3 ramp: 1, 3, 9, 27, 48...)."""
     from tests.parity_util import compare
-    _say("ragged M=12 d=3 chi=48 N=1000 chunk=384")
+    _say(f"ragged M=12 d=3 chi=48 N=1000 chunk=384 {form}")
     t = _chain(7, 12, 3, 48)
-    g = _run(mpsmod, t, 1000, seed=77, n_chunk=384, emit_n=1000)
-    rep = compare(t, 77, g)
+    g = _run(mpsmod, t, 1000, seed=77, n_chunk=384, emit_n=1000, precision=form)
+    rep = compare(t, 77, g, eps=EPS[form])
     print(rep)
 
 
-def test_several_k_and_column_tiles(mpsmod):
+@pytest.mark.parametrize("form", FORMS)
+def test_several_k_and_column_tiles(mpsmod, form):
     """chi=256: 16 K-steps of 16 and two column tiles per branch."""
     from tests.parity_util import compare
-    _say("chi=256 M=10 d=4 N=1536")
+    _say(f"chi=256 M=10 d=4 N=1536 {form}")
     t = _chain(8, 10, 4, 256)
-    g = _run(mpsmod, t, 1536, seed=5, emit_n=512)
-    rep = compare(t, 5, g)
+    g = _run(mpsmod, t, 1536, seed=5, emit_n=512, precision=form)
+    rep = compare(t, 5, g, eps=EPS[form])
     print(rep)
 
 
-def test_mixed_physical_dims_and_open_right_end(mpsmod):
+@pytest.mark.parametrize("form", FORMS)
+def test_mixed_physical_dims_and_open_right_end(mpsmod, form):
     """d_k in {1..6} per site, d=16 site, and chi_M > 1 (identity right environment)."""
     from tests.parity_util import compare
-    _say("mixed d, d=16 site, open right end")
+    _say(f"mixed d, d=16 site, open right end {form}")
     rng = np.random.default_rng(3)
     dl = [int(x) for x in rng.integers(1, 7, size=9)] + [16]
     chi = synth.ramp_bonds(dl, 40)
     chi[-1] = 3  # open right end wider than one
     chi[-2] = min(chi[-2], dl[-1] * 3)
     t = synth.to_c64(synth.random_mps(11, dl, chi))
-    g = _run(mpsmod, t, 777, seed=9, emit_n=777)
-    rep = compare(t, 9, g)
+    g = _run(mpsmod, t, 777, seed=9, emit_n=777, precision=form)
+    rep = compare(t, 9, g, eps=EPS[form])
     print(rep)
 
 
@@ -115,41 +123,44 @@ def test_product_state_closed_form(mpsmod):
         assert np.array_equal(g["outcomes"][~near, k], want[~near])
 
 
-def test_single_site_and_trivial_dims(mpsmod):
+@pytest.mark.parametrize("form", FORMS)
+def test_single_site_and_trivial_dims(mpsmod, form):
     from tests.parity_util import compare
-    _say("single site M=1 d=4; d=1 sites")
+    _say(f"single site M=1 d=4; d=1 sites {form}")
     a = synth.to_c64([synth.random_site(1, 0, 0, 1, 4, 1)])
-    g = _run(mpsmod, a, 500, seed=2, emit_n=500)
-    compare(a, 2, g)
+    g = _run(mpsmod, a, 500, seed=2, emit_n=500, precision=form)
+    compare(a, 2, g, eps=EPS[form])
     dl = [2, 1, 3, 1, 2]
     t = synth.to_c64(synth.random_mps(12, dl, synth.ramp_bonds(dl, 8)))
-    g = _run(mpsmod, t, 300, seed=2, emit_n=300)
+    g = _run(mpsmod, t, 300, seed=2, emit_n=300, precision=form)
     assert np.all(g["outcomes"][:, 1] == 0) and np.all(g["outcomes"][:, 3] == 0)
-    compare(t, 2, g)
+    compare(t, 2, g, eps=EPS[form])
 
 
-def test_chunking_and_offset_bit_exact(mpsmod):
+@pytest.mark.parametrize("form", FORMS)
+def test_chunking_and_offset_bit_exact(mpsmod, form):
     """Outcomes and logp depend only on the global sample index."""
-    _say("chunk/offset invariance M=16 d=4 chi=64 N=2000")
+    _say(f"chunk/offset invariance M=16 d=4 chi=64 N=2000 {form}")
     t = _chain(13, 16, 4, 64)
-    full = _run(mpsmod, t, 2000, seed=31)
-    chunked = _run(mpsmod, t, 2000, seed=31, n_chunk=300)
-    a = _run(mpsmod, t, 700, seed=31)
-    b = _run(mpsmod, t, 1300, seed=31, n_offset=700)
+    full = _run(mpsmod, t, 2000, seed=31, precision=form)
+    chunked = _run(mpsmod, t, 2000, seed=31, n_chunk=300, precision=form)
+    a = _run(mpsmod, t, 700, seed=31, precision=form)
+    b = _run(mpsmod, t, 1300, seed=31, n_offset=700, precision=form)
     assert np.array_equal(full["outcomes"], chunked["outcomes"])
     assert np.array_equal(full["logp"], chunked["logp"])
     assert np.array_equal(full["outcomes"], np.vstack([a["outcomes"], b["outcomes"]]))
     assert np.array_equal(full["logp"], np.concatenate([a["logp"], b["logp"]]))
-    again = _run(mpsmod, t, 2000, seed=31)
+    again = _run(mpsmod, t, 2000, seed=31, precision=form)
     assert np.array_equal(full["outcomes"], again["outcomes"]) and np.array_equal(full["logp"], again["logp"])
 
 
-def test_flagged_samples(mpsmod):
+@pytest.mark.parametrize("form", FORMS)
+def test_flagged_samples(mpsmod, form):
     """A zero site tensor stops every sample: MPS_ENUMERIC, -1 outcomes, -inf logp."""
-    _say("flagged samples: zero tensor at site 3")
+    _say(f"flagged samples: zero tensor at site 3 {form}")
     t = _chain(14, 8, 3, 9)
     t[3] = np.zeros_like(t[3])
-    g = _run(mpsmod, t, 400, seed=1)
+    g = _run(mpsmod, t, 400, seed=1, precision=form)
     assert g["status"] == mpsmod.MPS_ENUMERIC
     assert g["stats"].flagged == 400
     assert np.all(g["outcomes"][:, 3:] == -1) and np.all(g["outcomes"][:, :3] >= 0)
@@ -173,15 +184,16 @@ def test_empty_and_memory_cap(mpsmod):
     s.close()
 
 
-def test_brute_force_distribution_on_gpu(mpsmod):
+@pytest.mark.parametrize("form", FORMS)
+def test_brute_force_distribution_on_gpu(mpsmod, form):
     """TV of 10^6 GPU samples against brute-force enumeration on a tiny chain."""
     import oracle
-    _say("GPU TV vs brute force M=6 d=2 chi=4 N=1e6")
+    _say(f"GPU TV vs brute force M=6 d=2 chi=4 N=1e6 {form}")
     M, d, chi = 6, 2, 4
     t128 = synth.random_mps(106, [d] * M, synth.ramp_bonds([d] * M, chi))
     t = synth.to_c64(t128)
     configs, p = oracle.brute_force(synth.promote(t))
-    g = _run(mpsmod, t, 10**6, seed=2024)
+    g = _run(mpsmod, t, 10**6, seed=2024, precision=form)
     hist = np.bincount(oracle.config_index(g["outcomes"], [d] * M), minlength=len(p)) / 10**6
     tv = 0.5 * np.abs(hist[oracle.config_index(configs, [d] * M)] - p).sum()
     assert tv <= 5e-3, tv
