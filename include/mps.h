@@ -81,10 +81,39 @@ typedef struct {
    * Either pointer may be NULL.  emit_n = 0 disables both.                     */
   int64_t emit_n;
   int32_t emit_dmax;
-  int32_t reserved;
+  /* Contraction tile order: workgroups resident on one XCD cover tile_group
+   * row blocks by several column tiles (operand reuse in L2).  0 = library
+   * default, 1 = row-major order.                                             */
+  int32_t tile_group;
   double* emit_probs;
   double* emit_u;
+  /* 1: capture the launches of one chunk (all sites) in a HIP graph and replay
+   * it for every chunk of the call.  Needs a non-NULL stream; ignored when
+   * profile is set or the call has a single chunk.                         */
+  int32_t graph;
+  int32_t reserved;
+  /* Optional per-sample displacement of the physical index (MPS-based GBS
+   * simulation, Section 3.4.1): DEVICE complex64 mu[N][M] (row of the call,
+   * site), caller-owned, or NULL.  At site k the contraction output of row n
+   * is replaced by D(mu[n][k]) W before the branch weights are formed, with
+   * D(mu) = exp(-|mu|^2/2) exp(mu a^+) exp(-mu^* a) on the d_k-level Fock
+   * space (Eq. 7; both factors are triangular, so this d x d product equals
+   * the corresponding block of the untruncated displacement operator).
+   * Ignored by mps_sample_batch.                                            */
+  const void* displace;
 } mps_options;
+
+/* One chain of a batched call (mps_sample_batch); fields as in mps_sample. */
+typedef struct {
+  const void* const* tensors;  /* host array of M device pointers           */
+  const int32_t* chi;          /* host array of M+1 bond dimensions          */
+  const int32_t* d;            /* host array of M physical dimensions        */
+  int32_t M;
+  int32_t reserved;
+  uint64_t mps_id;             /* second generator key word of this chain    */
+  int32_t* outcomes;           /* device int32 [N][M], caller-owned          */
+  double* logp;                /* device double [N] or NULL                  */
+} mps_chain;
 
 typedef struct {
   int64_t contract_launches;  /* contraction kernels launched by the last call     */
@@ -144,7 +173,22 @@ int mps_sample(mps_handle h, const void* const* tensors, int32_t dtype,
                int64_t N, int64_t n_offset, uint64_t seed,
                int32_t* outcomes, double* logp);
 
-/* Counters of the last mps_sample call on this handle. */
+/*
+ * Draw N samples (global indices n_offset .. n_offset+N-1) from each of B
+ * independent chains in one sweep: at every site index k, one contraction,
+ * one measurement (and, for 16-bit forms, one packing) launch advance all
+ * chains that have a site k; chains may differ in M, chi and d.  Chain b uses
+ * generator key (seed, chains[b].mps_id), so its outcomes are bit-identical
+ * to mps_sample on that chain alone with options.mps_id = chains[b].mps_id.
+ * Section 3.1 (data parallelism over samples) applied across chains; the
+ * site-varying bond dimensions follow Section 3.4.2.  The handle's options
+ * apply (precision, chunk, stream, cap, profile); debug emits are ignored.
+ * Returns as mps_sample; MPS_ENUMERIC counts flagged samples over all chains.
+ */
+int mps_sample_batch(mps_handle h, int32_t B, const mps_chain* chains, int32_t dtype,
+                     int64_t N, int64_t n_offset, uint64_t seed);
+
+/* Counters of the last mps_sample / mps_sample_batch call on this handle. */
 int mps_get_stats(mps_handle h, mps_stats* st);
 
 /* Message of the last failing call on this thread ("" if none). */

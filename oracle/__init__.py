@@ -8,11 +8,12 @@ sampling arithmetic.
 
 * ``philox``  -- Philox4x64-10 and the FP64 uniform per (seed, chain, sample, site).
 * ``sampler`` -- the sequential sampler (Section 2.2; Section 3.3.1, Algorithm 1),
-  its forced-prefix mode, the direct amplitude product and brute-force
-  enumeration used to pin it.
+  its forced-prefix mode, the optional per-sample displacement of the
+  physical index (Section 3.4.1, Eq. 7), the direct amplitude product and
+  brute-force enumeration used to pin it.
 
 Every function is pinned by a CPU test (closed forms, invariants, brute force,
 a library cross-check); none is "parity unpinned".
 """
 from .philox import philox4x64, philox4x64_np, uniforms, bits_to_uniform  # noqa: F401
-from .sampler import sample, forced_probs, draw, amplitude_norm2, brute_force, config_index  # noqa: F401
+from .sampler import sample, forced_probs, draw, amplitude_norm2, brute_force, config_index, displacement  # noqa: F401

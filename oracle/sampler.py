@@ -59,16 +59,44 @@ def _check_chain(tensors):
         assert a.shape[2] == b.shape[0], "bond mismatch"
 
 
+def displacement(mu: np.ndarray, d: int) -> np.ndarray:
+    """Displacement operators D(mu) on a d-level Fock space, one per entry of mu.
+
+    Eq. 7 (Section 3.4.1): D(mu) = e^{-|mu|^2/2} e^{mu a^+} e^{-mu^* a}.  Both
+    factors are exponentials of nilpotent matrices, so each is its finite power
+    series sum_{k<d} X^k / k!, summed here term by term.  Returns an array of
+    shape mu.shape + (d, d), complex128.
+    """
+    mu = np.asarray(mu, dtype=np.complex128)
+    a = np.diag(np.sqrt(np.arange(1, d, dtype=np.float64)), 1).astype(np.complex128)  # a|n> = sqrt(n)|n-1>
+    ad = a.T.copy()
+    X = mu[..., None, None] * ad  # mu a^+
+    Y = -np.conj(mu)[..., None, None] * a  # -mu^* a
+    eye = np.broadcast_to(np.eye(d, dtype=np.complex128), X.shape)
+    EX, EY = eye.copy(), eye.copy()
+    PX, PY = eye.copy(), eye.copy()
+    for k in range(1, d):
+        PX = PX @ X / k
+        PY = PY @ Y / k
+        EX = EX + PX
+        EY = EY + PY
+    return np.exp(-np.abs(mu) ** 2 / 2)[..., None, None] * (EX @ EY)
+
+
 def sample(tensors, seed: int, N: int, n_offset: int = 0, mps_id: int = 0,
            forced: np.ndarray | None = None, want_probs: bool = False,
-           n_index: np.ndarray | None = None):
+           n_index: np.ndarray | None = None, displace: np.ndarray | None = None):
     """Sample N configurations (global indices n_offset .. n_offset+N-1, or
     the explicit global indices ``n_index`` when given).
 
     tensors: list of M complex arrays (chi_k, d_k, chi_{k+1}); promoted to
     complex128.  With ``forced`` (int array [N, M]) the chosen branch at each
     site is taken from it instead of the draw: the forced-prefix mode used to
-    read the conditional probabilities along another sampler's path.
+    read the conditional probabilities along another sampler's path.  With
+    ``displace`` (complex [N, M]) the physical index of each sample's W is
+    transformed by the displacement operator D(mu[n, k]) before the branch
+    weights are formed (the per-sample random displacement of MPS-based GBS
+    simulation, Section 3.4.1).
 
     Returns a dict with
       outcomes [N, M] int32  (-1 after a sample stops),
@@ -105,6 +133,8 @@ def sample(tensors, seed: int, N: int, n_offset: int = 0, mps_id: int = 0,
         chi_l, d, chi_r = A.shape
         assert l.shape[1] == chi_l
         W = (l @ A.reshape(chi_l, d * chi_r)).reshape(N, d, chi_r)
+        if displace is not None:
+            W = displacement(np.asarray(displace)[:, k], d) @ W
         q = np.sum(W.real ** 2 + W.imag ** 2, axis=2)
         P = np.cumsum(q, axis=1)
         S = P[:, d - 1]
@@ -139,10 +169,10 @@ def sample(tensors, seed: int, N: int, n_offset: int = 0, mps_id: int = 0,
 
 
 def forced_probs(tensors, outcomes: np.ndarray, seed: int, n_offset: int = 0, mps_id: int = 0,
-                 n_index: np.ndarray | None = None):
+                 n_index: np.ndarray | None = None, displace: np.ndarray | None = None):
     """Conditional probabilities p_k(i | s_0..s_{k-1}) along given outcomes."""
     return sample(tensors, seed, outcomes.shape[0], n_offset=n_offset, mps_id=mps_id,
-                  forced=outcomes, n_index=n_index)
+                  forced=outcomes, n_index=n_index, displace=displace)
 
 
 # --------------------------------------------------------------------------

@@ -21,6 +21,7 @@
 // multiply-add, the algorithmic count.
 
 #include "sweep.h"
+#include "tiling.h"
 
 #include <math.h>
 
@@ -58,19 +59,17 @@ static_assert(BM == 128 && BNC == 64, "wave layout below assumes a 128 x 64 (com
 // of order u*sqrt(K) per output; blocking it into K/BK partial sums cuts that
 // by about sqrt(BK), which matters because the rounding error of the left
 // vector is carried from site to site.
-__global__ __launch_bounds__(NTHR, 2) void contract_f32_kernel(ContractArgs a, int tiles_m, int tiles_n,
-                                                              int per_xcd) {
+__global__ __launch_bounds__(NTHR, 2) void contract_f32_kernel(const ContractProb* probs, const int* tn_start,
+                                                              int nprob, int tn_total, int tiles_m, int per_xcd,
+                                                              int group_m, const ChunkArgs* chp) {
   __shared__ float lds[2 * STAGE];
+  const int rows = chp->rows;
 
-  // Workgroups are dealt round-robin to the 8 XCDs.  Give each XCD a
-  // contiguous run of tiles, columns fastest: the workgroups resident on one
-  // XCD then share one L row block in their L2 while they sweep the column
-  // tiles of the site tensor (which every XCD streams from the MALL).
-  const int b = blockIdx.x;
-  const int t = (b & 7) * per_xcd + (b >> 3);
-  if (t >= tiles_m * tiles_n) return;
-  const int tm = t / tiles_n;
-  const int tn = t - tm * tiles_n;
+  int tm, tng;
+  if (!map_tile(blockIdx.x, tiles_m, tn_total, per_xcd, group_m, tm, tng)) return;
+  const int p = find_problem(tn_start, nprob, tng);
+  const ContractProb a = probs[p];
+  const int tn = tng - tn_start[p];
   const int T = col_tiles(a.chi_r);
   const int branch = tn / T;
   const int ct = tn - branch * T;
@@ -91,7 +90,7 @@ __global__ __launch_bounds__(NTHR, 2) void contract_f32_kernel(ContractArgs a, i
   float2 areg[ALOADS];
   // Interior tiles (all rows, K and columns in range: every tile of a
   // plateau site) load without masks; edge tiles zero what is out of range.
-  const bool rows_full = m0 + BM <= a.rows;
+  const bool rows_full = m0 + BM <= rows;
   const bool cols_full = c0 + BNC <= a.chi_r;
   auto gload = [&](int k0) {
     if (rows_full && cols_full && k0 + BK <= a.K) {
@@ -113,7 +112,7 @@ __global__ __launch_bounds__(NTHR, 2) void contract_f32_kernel(ContractArgs a, i
         const int idx = it * NTHR + tid;
         const int r = idx / BK, c = idx % BK;
         const int gr = m0 + r, gk = k0 + c;
-        lreg[it] = (gr < a.rows && gk < a.K) ? a.L[(size_t)gr * a.K + gk] : make_float2(0.f, 0.f);
+        lreg[it] = (gr < rows && gk < a.K) ? a.L[(size_t)gr * a.K + gk] : make_float2(0.f, 0.f);
       }
 #pragma unroll
       for (int it = 0; it < ALOADS; ++it) {
@@ -198,7 +197,7 @@ __global__ __launch_bounds__(NTHR, 2) void contract_f32_kernel(ContractArgs a, i
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const int gr = m0 + wr + rb * 32 + (v >> 2) * 8 + half * 4 + (v & 3);
-          if (gr < a.rows) Wf[(size_t)gr * wpitch + fcol] = tot[rb][cb][v];
+          if (gr < rows) Wf[(size_t)gr * wpitch + fcol] = tot[rb][cb][v];
         }
       }
     }
@@ -224,19 +223,20 @@ __global__ __launch_bounds__(NTHR, 2) void contract_f32_kernel(ContractArgs a, i
   __syncthreads();
   if (tid < BM) {
     const int gr = m0 + tid;
-    if (gr < a.rows) a.qpart[(size_t)gr * (a.d * T) + branch * T + ct] = red[tid] + red[BM + tid];
+    if (gr < rows) a.qpart[(size_t)gr * (a.d * T) + branch * T + ct] = red[tid] + red[BM + tid];
   }
 }
 
 }  // namespace
 
-hipError_t launch_contract_f32(const ContractArgs& a, hipStream_t s) {
-  const int tiles_m = (a.rows + BM - 1) / BM;
-  const int tiles_n = a.d * col_tiles(a.chi_r);
-  const long long ntiles = (long long)tiles_m * tiles_n;
-  if (ntiles <= 0) return hipSuccess;
+hipError_t launch_contract_f32(const ContractProb* probs, const int* tn_start, int nprob, int tn_total,
+                               const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s) {
+  const int tiles_m = (grid_rows + BM - 1) / BM;
+  const long long ntiles = (long long)tiles_m * tn_total;
+  if (ntiles <= 0 || nprob <= 0) return hipSuccess;
   const int per_xcd = (int)((ntiles + 7) / 8);
-  hipLaunchKernelGGL(contract_f32_kernel, dim3(per_xcd * 8), dim3(NTHR), 0, s, a, tiles_m, tiles_n, per_xcd);
+  hipLaunchKernelGGL(contract_f32_kernel, dim3(per_xcd * 8), dim3(NTHR), 0, s, probs, tn_start, nprob, tn_total,
+                     tiles_m, per_xcd, group_m, ch);
   return hipGetLastError();
 }
 

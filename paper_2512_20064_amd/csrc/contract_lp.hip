@@ -16,13 +16,15 @@
 // (Re a, -Im a) for p = 0 (real part of W) and (Im a, Re a) for p = 1
 // (imaginary part).  pack_kernel writes that embedding once per site,
 // transposed so that K is contiguous ("NT" operands: both MFMA operands are
-// 16-byte runs of K), each branch padded with zero columns to a multiple of
-// 128 complex columns and K padded with zeros to a multiple of 64.  The
+// 16-byte runs of K) and K-blocked (see kblk_off), each branch padded with
+// zero columns to a multiple of 128 complex columns and K padded with zeros
+// to a multiple of 64.  The
 // embedding does exactly the algorithmic 8 real flops per complex
 // multiply-add; its cost is that the site-tensor operand is twice as large
 // as the complex data, which only matters for L2/LDS traffic.
 
 #include "sweep.h"
+#include "tiling.h"
 
 namespace mps {
 namespace {
@@ -57,11 +59,15 @@ constexpr int PK_C = 64;   // complex columns per tile
 constexpr int PK_P = PK_C + 1;
 
 template <typename T, int NPROD>
-__global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
+__global__ __launch_bounds__(256) void pack_kernel(const PackProb* probs, const int* blk_start, int nprob) {
   __shared__ float2 tile[PK_L][PK_P];
-  const int c0 = blockIdx.x * PK_C;
-  const int l0 = blockIdx.y * PK_L;
-  const int br = blockIdx.z;
+  const int p = find_problem(blk_start, nprob, blockIdx.x);
+  const PackProb a = probs[p];
+  const int lb = blockIdx.x - blk_start[p];
+  const int ncb = a.CP / PK_C, nlb = a.Kp / (2 * PK_L);
+  const int c0 = (lb % ncb) * PK_C;
+  const int l0 = ((lb / ncb) % nlb) * PK_L;
+  const int br = lb / (ncb * nlb);
   const int tid = threadIdx.x;
   const size_t pitch = (size_t)a.d * a.chi_r;
 #pragma unroll
@@ -96,7 +102,7 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
       lo[e] = (T)(v[e] - (float)h[e]);
     }
     const size_t orow = ((size_t)br * a.CP + c0 + c) * 2 + p;
-    const size_t off = orow * a.Kp + 2 * l0 + ch * 8;
+    const size_t off = kblk_off(orow, 2 * l0 + ch * 8, a.Kp);
     *reinterpret_cast<typename Vec8<T>::type*>(Bh + off) = h;
     if (NPROD == 3) *reinterpret_cast<typename Vec8<T>::type*>(Bl + off) = lo;
   }
@@ -106,36 +112,52 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
 
 constexpr int BM = kLpBM;            // rows (samples) per workgroup
 constexpr int BN = 2 * kLpBNC;       // real columns per workgroup
-constexpr int BK = kLpBK;            // real K per stage
+constexpr int BK = kLpBK;            // real K per pipeline stage
 constexpr int NTHR = 512;            // 8 waves: 4 (rows) x 2 (columns)
-constexpr int ARR = BM * BK * 2;     // bytes of one operand array in a stage
-static_assert(BM == 256 && BN == 256 && BK == 32, "layout below assumes 256 x 256 x 32");
+constexpr int NST = 4;               // pipeline stages in LDS
+constexpr int ARR = BM * BK * 2;     // bytes of one operand tile in a stage (8 KiB)
+static_assert(BM == 256 && BN == 256 && BK == 16, "layout below assumes 256 x 256 x 16");
 
-// LDS rows are 64 bytes (32 16-bit K values = 4 chunks of 16 bytes).  The
-// chunk index is XOR-swizzled by row so that the 16-byte reads of 8 or 16
+// LDS rows are 32 bytes (16 K values = 2 chunks of 16 bytes).  The chunk is
+// XOR-swizzled by row bits 2 and 3 so that the 16-byte reads of 8 or 16
 // consecutive lanes (consecutive rows, same chunk) land in distinct banks.
-__device__ inline int swz(int row) { return ((row >> 1) ^ (row >> 3)) & 3; }
-__device__ inline int lds_off(int row, int chunk) { return row * 64 + ((chunk ^ swz(row)) << 4); }
+__device__ inline int swz(int row) { return ((row >> 2) ^ (row >> 3)) & 1; }
+__device__ inline int lds_off(int row, int chunk) { return row * 32 + ((chunk ^ swz(row)) << 4); }
 
+// s_waitcnt immediate waiting for at most n outstanding vector-memory
+// operations (n < 16) and nothing else.
+constexpr unsigned vmcnt_imm(unsigned n) { return (n & 0xF) | (0x7u << 4) | (0xFu << 8); }
+
+// Pipeline: stage kt lives in LDS buffer kt % 4.  Operand tiles go straight
+// from memory into LDS (global_load_lds_dwordx4: no staging registers and no
+// LDS store phase), three stages ahead of the MFMAs.  At the top of stage kt
+// each wave waits for its own loads of stage kt (later stages stay in
+// flight), then one barrier makes every wave's data visible and guarantees
+// that every wave is done with stage kt-1, whose buffer the loads of stage
+// kt+3 then overwrite.
 template <typename T, int NPROD>
-__global__ __launch_bounds__(NTHR, 1) void contract_lp_kernel(ContractLpArgs a, int tiles_m, int tiles_n,
-                                                             int per_xcd) {
+__global__ __launch_bounds__(NTHR, 1) void contract_lp_kernel(const ContractLpProb* probs, const int* tn_start,
+                                                             int nprob, int tn_total, int tiles_m, int per_xcd,
+                                                             int group_m, const ChunkArgs* chp) {
   typedef typename Vec8<T>::type V8;
   constexpr int NARR = NPROD == 3 ? 4 : 2;  // Ah, [Al], Bh, [Bl]
   constexpr int STAGE = NARR * ARR;
-  __shared__ __attribute__((aligned(16))) char lds[2 * STAGE];
+  constexpr int IPW = NARR;                 // 1 KiB load instructions per wave per stage
+  constexpr int IB = NARR / 2;              // index of the Bh tile in a stage
+  __shared__ __attribute__((aligned(16))) char lds[NST * STAGE];
 
-  const int b = blockIdx.x;
-  const int t = (b & 7) * per_xcd + (b >> 3);
-  if (t >= tiles_m * tiles_n) return;
-  const int tm = t / tiles_n;
-  const int tn = t - tm * tiles_n;
+  int tm, tng;
+  if (!map_tile(blockIdx.x, tiles_m, tn_total, per_xcd, group_m, tm, tng)) return;
+  const int rows = chp->rows;
+  const int p = find_problem(tn_start, nprob, tng);
+  const ContractLpProb a = probs[p];
+  const int tn = tng - tn_start[p];
   const int T_ = a.CP / kLpBNC;
   const int branch = tn / T_;
   const int ct = tn - branch * T_;
   const int m0 = tm * BM;
-  const int c0 = ct * kLpBNC;  // first complex column within the branch
-  const size_t brow0 = ((size_t)branch * a.CP + c0) * 2;  // first packed real column
+  const int c0 = ct * kLpBNC;                               // first complex column within the branch
+  const size_t cblk = ((size_t)branch * a.CP + c0) * 2 / BM;  // 256-row block of the packed tensor
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -145,45 +167,29 @@ __global__ __launch_bounds__(NTHR, 1) void contract_lp_kernel(ContractLpArgs a, 
   const int half = lane >> 5;
   const int j = lane & 31;
 
-  // Operand arrays of a stage: q = 0 Ah, 1 Al, 2 Bh, 3 Bl (NARR == 2: Ah, Bh).
-  const T* const pAh = (const T*)a.Lh + (size_t)m0 * a.Kp;
-  const T* const pAl = NPROD == 3 ? (const T*)a.Ll + (size_t)m0 * a.Kp : pAh;
-  const T* const pBh = (const T*)a.Bh + brow0 * a.Kp;
-  const T* const pBl = NPROD == 3 ? (const T*)a.Bl + brow0 * a.Kp : pBh;
-  constexpr int IB = NARR / 2;  // index of the Bh array in a stage
-
-  // global -> register prefetch: 2 chunks of 16 bytes per array per thread.
-  // Plain registers (no array) so that nothing is placed in scratch.
-  const int row0 = tid >> 2, row1 = (NTHR + tid) >> 2, chk = tid & 3;
-  const size_t g0 = (size_t)row0 * a.Kp + chk * 8, g1 = (size_t)row1 * a.Kp + chk * 8;
-  const int s0 = lds_off(row0, chk), s1 = lds_off(row1, chk);
-  uint4 pAh0, pAh1, pAl0, pAl1, pBh0, pBh1, pBl0, pBl1;
-#define MPS_GLOAD(k0)                                                   \
-  do {                                                                  \
-    pAh0 = *reinterpret_cast<const uint4*>(pAh + g0 + (k0));            \
-    pAh1 = *reinterpret_cast<const uint4*>(pAh + g1 + (k0));            \
-    pBh0 = *reinterpret_cast<const uint4*>(pBh + g0 + (k0));            \
-    pBh1 = *reinterpret_cast<const uint4*>(pBh + g1 + (k0));            \
-    if (NPROD == 3) {                                                   \
-      pAl0 = *reinterpret_cast<const uint4*>(pAl + g0 + (k0));          \
-      pAl1 = *reinterpret_cast<const uint4*>(pAl + g1 + (k0));          \
-      pBl0 = *reinterpret_cast<const uint4*>(pBl + g0 + (k0));          \
-      pBl1 = *reinterpret_cast<const uint4*>(pBl + g1 + (k0));          \
-    }                                                                   \
-  } while (0)
-#define MPS_SSTORE(st)                                                  \
-  do {                                                                  \
-    *reinterpret_cast<uint4*>((st) + 0 * ARR + s0) = pAh0;              \
-    *reinterpret_cast<uint4*>((st) + 0 * ARR + s1) = pAh1;              \
-    *reinterpret_cast<uint4*>((st) + IB * ARR + s0) = pBh0;             \
-    *reinterpret_cast<uint4*>((st) + IB * ARR + s1) = pBh1;             \
-    if (NPROD == 3) {                                                   \
-      *reinterpret_cast<uint4*>((st) + 1 * ARR + s0) = pAl0;            \
-      *reinterpret_cast<uint4*>((st) + 1 * ARR + s1) = pAl1;            \
-      *reinterpret_cast<uint4*>((st) + 3 * ARR + s0) = pBl0;            \
-      *reinterpret_cast<uint4*>((st) + 3 * ARR + s1) = pBl1;            \
-    }                                                                   \
-  } while (0)
+  // This wave's load instructions: tile q, row group rg (32 rows = 1 KiB).
+  const size_t kbs = (size_t)(a.Kp / BK) * 4096;  // elements per 256-row block
+  const T* src[IPW];
+  int ldst[IPW];
+#pragma unroll
+  for (int i = 0; i < IPW; ++i) {
+    const int idx = wave * IPW + i;
+    const int q = idx >> 3, rg = idx & 7;
+    const bool is_b = q >= IB;
+    const int qq = is_b ? q - IB : q;  // 0 = hi, 1 = lo
+    const T* base = is_b ? (const T*)(qq ? a.Bl : a.Bh) + cblk * kbs : (const T*)(qq ? a.Ll : a.Lh) + (size_t)tm * kbs;
+    const int row = rg * 32 + (lane >> 1);
+    const int lc = (lane & 1) ^ swz(row);
+    src[i] = base + row * 16 + lc * 8;
+    ldst[i] = q * ARR + rg * 1024;
+  }
+  auto issue = [&](int kt) {
+    char* st = lds + (kt % NST) * STAGE;
+#pragma unroll
+    for (int i = 0; i < IPW; ++i)
+      __builtin_amdgcn_global_load_lds((const void*)(src[i] + (size_t)kt * 4096),
+                                       (__attribute__((address_space(3))) void*)(st + ldst[i]), 16, 0, 0);
+  };
 
   floatx16 acc[2][4];
   const floatx16 zero = {};
@@ -192,43 +198,43 @@ __global__ __launch_bounds__(NTHR, 1) void contract_lp_kernel(ContractLpArgs a, 
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = zero;
 
-  const int nkt = a.Kp / BK;
-  MPS_GLOAD(0);
-  MPS_SSTORE(lds);
-  __syncthreads();
+  const int nkt = a.Kp / BK;  // >= 4: Kp is a multiple of 64
+  issue(0);
+  issue(1);
+  issue(2);
   for (int kt = 0; kt < nkt; ++kt) {
-    char* st = lds + (kt & 1) * STAGE;
-    if (kt + 1 < nkt) MPS_GLOAD((kt + 1) * BK);
+    const int later = min(2, nkt - 1 - kt);
+    if (later == 2) __builtin_amdgcn_s_waitcnt(vmcnt_imm(2 * IPW));
+    else if (later == 1) __builtin_amdgcn_s_waitcnt(vmcnt_imm(IPW));
+    else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+    asm volatile("s_barrier" ::: "memory");
+    if (kt + 3 < nkt) issue(kt + 3);
+    const char* st = lds + (kt % NST) * STAGE;
+    V8 ah[2], al[2], bh[4], bl[4];
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      const int ch = ks * 2 + half;
-      V8 ah[2], al[2], bh[4], bl[4];
+    for (int rb = 0; rb < 2; ++rb) {
+      const int row = wr + rb * 32 + j;
+      ah[rb] = *reinterpret_cast<const V8*>(st + 0 * ARR + lds_off(row, half));
+      if (NPROD == 3) al[rb] = *reinterpret_cast<const V8*>(st + 1 * ARR + lds_off(row, half));
+    }
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb) {
-        const int row = wr + rb * 32 + j;
-        ah[rb] = *reinterpret_cast<const V8*>(st + 0 * ARR + lds_off(row, ch));
-        if (NPROD == 3) al[rb] = *reinterpret_cast<const V8*>(st + 1 * ARR + lds_off(row, ch));
-      }
+    for (int cb = 0; cb < 4; ++cb) {
+      const int row = wc + cb * 32 + j;
+      bh[cb] = *reinterpret_cast<const V8*>(st + IB * ARR + lds_off(row, half));
+      if (NPROD == 3) bl[cb] = *reinterpret_cast<const V8*>(st + 3 * ARR + lds_off(row, half));
+    }
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) {
-        const int row = wc + cb * 32 + j;
-        bh[cb] = *reinterpret_cast<const V8*>(st + IB * ARR + lds_off(row, ch));
-        if (NPROD == 3) bl[cb] = *reinterpret_cast<const V8*>(st + 3 * ARR + lds_off(row, ch));
-      }
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-          acc[rb][cb] = Vec8<T>::mfma(ah[rb], bh[cb], acc[rb][cb]);
-          if (NPROD == 3) {
-            acc[rb][cb] = Vec8<T>::mfma(ah[rb], bl[cb], acc[rb][cb]);
-            acc[rb][cb] = Vec8<T>::mfma(al[rb], bh[cb], acc[rb][cb]);
-          }
+        acc[rb][cb] = Vec8<T>::mfma(ah[rb], bh[cb], acc[rb][cb]);
+        if (NPROD == 3) {
+          acc[rb][cb] = Vec8<T>::mfma(ah[rb], bl[cb], acc[rb][cb]);
+          acc[rb][cb] = Vec8<T>::mfma(al[rb], bh[cb], acc[rb][cb]);
         }
-    }
-    if (kt + 1 < nkt) MPS_SSTORE(lds + ((kt + 1) & 1) * STAGE);
-    __syncthreads();
+      }
   }
+  __syncthreads();  // the stage buffers are reused below
 
   // Epilogue 1: W.  Output lane (j, half) of a 32x32 block holds real column j
   // and rows 8*(v/4) + 4*half + v%4.
@@ -246,7 +252,7 @@ __global__ __launch_bounds__(NTHR, 1) void contract_lp_kernel(ContractLpArgs a, 
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const int gr = m0 + wr + rb * 32 + (v >> 2) * 8 + half * 4 + (v & 3);
-          if (gr < a.rows) Wf[(size_t)gr * wpitch + fcol] = acc[rb][cb][v];
+          if (gr < rows) Wf[(size_t)gr * wpitch + fcol] = acc[rb][cb][v];
         }
       }
     }
@@ -271,40 +277,41 @@ __global__ __launch_bounds__(NTHR, 1) void contract_lp_kernel(ContractLpArgs a, 
   __syncthreads();
   if (tid < BM) {
     const int gr = m0 + tid;
-    if (gr < a.rows) a.qpart[(size_t)gr * (a.d * T_) + branch * T_ + ct] = red[tid] + red[BM + tid];
+    if (gr < rows) a.qpart[(size_t)gr * (a.d * T_) + branch * T_ + ct] = red[tid] + red[BM + tid];
   }
 }
 
-#undef MPS_GLOAD
-#undef MPS_SSTORE
-
 template <typename T, int NPROD>
-hipError_t launch_pack_t(const PackArgs& a, hipStream_t s) {
-  const dim3 grid(a.CP / PK_C, a.Kp / (2 * PK_L), a.d);
-  hipLaunchKernelGGL((pack_kernel<T, NPROD>), grid, dim3(256), 0, s, a);
+hipError_t launch_pack_t(const PackProb* probs, const int* blk_start, int nprob, int blk_total, hipStream_t s) {
+  if (nprob <= 0 || blk_total <= 0) return hipSuccess;
+  hipLaunchKernelGGL((pack_kernel<T, NPROD>), dim3(blk_total), dim3(256), 0, s, probs, blk_start, nprob);
   return hipGetLastError();
 }
 
 template <typename T, int NPROD>
-hipError_t launch_contract_t(const ContractLpArgs& a, hipStream_t s) {
-  const int tiles_m = (a.rows + BM - 1) / BM;
-  const int tiles_n = a.d * (a.CP / kLpBNC);
-  const long long ntiles = (long long)tiles_m * tiles_n;
-  if (ntiles <= 0) return hipSuccess;
+hipError_t launch_contract_t(const ContractLpProb* probs, const int* tn_start, int nprob, int tn_total,
+                             const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s) {
+  const int tiles_m = (grid_rows + BM - 1) / BM;
+  const long long ntiles = (long long)tiles_m * tn_total;
+  if (ntiles <= 0 || nprob <= 0) return hipSuccess;
   const int per_xcd = (int)((ntiles + 7) / 8);
-  hipLaunchKernelGGL((contract_lp_kernel<T, NPROD>), dim3(per_xcd * 8), dim3(NTHR), 0, s, a, tiles_m, tiles_n,
-                     per_xcd);
+  hipLaunchKernelGGL((contract_lp_kernel<T, NPROD>), dim3(per_xcd * 8), dim3(NTHR), 0, s, probs, tn_start, nprob,
+                     tn_total, tiles_m, per_xcd, group_m, ch);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_pack_lp(int form, const PackArgs& a, hipStream_t s) {
-  return form == kBf16x3 ? launch_pack_t<bf16_t, 3>(a, s) : launch_pack_t<f16_t, 1>(a, s);
+hipError_t launch_pack_lp(int form, const PackProb* probs, const int* blk_start, int nprob, int blk_total,
+                          hipStream_t s) {
+  return form == kBf16x3 ? launch_pack_t<bf16_t, 3>(probs, blk_start, nprob, blk_total, s)
+                         : launch_pack_t<f16_t, 1>(probs, blk_start, nprob, blk_total, s);
 }
 
-hipError_t launch_contract_lp(int form, const ContractLpArgs& a, hipStream_t s) {
-  return form == kBf16x3 ? launch_contract_t<bf16_t, 3>(a, s) : launch_contract_t<f16_t, 1>(a, s);
+hipError_t launch_contract_lp(int form, const ContractLpProb* probs, const int* tn_start, int nprob, int tn_total,
+                              const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s) {
+  return form == kBf16x3 ? launch_contract_t<bf16_t, 3>(probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s)
+                         : launch_contract_t<f16_t, 1>(probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s);
 }
 
 }  // namespace mps

@@ -10,6 +10,14 @@
 //   l'    = W[s, :] / sqrt(q_s), written in the operand format of the next
 //           contraction (FP32 complex, or 16-bit hi/lo planes).
 //
+// With a per-sample displacement mu (MPS-based GBS simulation, Section
+// 3.4.1) W is first replaced by D(mu) W over the physical index; D is built
+// per sample from the closed form of Eq. 7 into the wave's LDS (the paper
+// computes a batch of them with the batch index last; here each wave builds
+// its own sample's D next to the data it transforms), and the branch weights
+// are then formed from W' directly instead of from the contraction's
+// partial sums.
+//
 // The paper rescales each sample by its own maximum so that low precision
 // keeps its range (Section 3.3.1); dividing by the 2-norm of the chosen branch
 // does the same job, keeps every element of l' within [-1, 1], and the scale
@@ -63,64 +71,159 @@ struct LWriter;
 template <>
 struct LWriter<kOutF32> {
   float2* dst;
-  __device__ LWriter(const MeasureArgs& a, int row) : dst(a.Lout + (size_t)row * a.chi_r) {}
+  __device__ LWriter(const MeasureProb& a, int row) : dst(a.Lout + (size_t)row * a.chi_r) {}
   __device__ void put(int r, float x, float y) { dst[r] = make_float2(x, y); }
-  __device__ void pad(const MeasureArgs&, int) {}
+  __device__ void pad(const MeasureProb&, int) {}
 };
 
 template <>
 struct LWriter<kOutBf16x2> {
-  bf16_t* hi;
-  bf16_t* lo;
-  __device__ LWriter(const MeasureArgs& a, int row)
-      : hi((bf16_t*)a.Lh + (size_t)row * a.ld_out), lo((bf16_t*)a.Ll + (size_t)row * a.ld_out) {}
+  uint32_t* hi;
+  uint32_t* lo;
+  size_t row;
+  int ld;
+  __device__ LWriter(const MeasureProb& a, int r)
+      : hi((uint32_t*)a.Lh), lo((uint32_t*)a.Ll), row((size_t)r), ld(a.ld_out) {}
+  // x = hi + lo with hi = bf16(x) (round to nearest even), lo = bf16(x - hi);
+  // (re, im) of complex r are K elements 2r, 2r+1: one 32-bit word.
   __device__ void put(int r, float x, float y) {
-    // x = hi + lo with hi = bf16(x) (round to nearest even), lo = bf16(x - hi)
     const bf16_t xh = (bf16_t)x, yh = (bf16_t)y;
     const bf16_t xl = (bf16_t)(x - (float)xh), yl = (bf16_t)(y - (float)yh);
-    hi[2 * r] = xh;
-    hi[2 * r + 1] = yh;
-    lo[2 * r] = xl;
-    lo[2 * r + 1] = yl;
+    const size_t w = kblk_off(row, 2 * r, ld) >> 1;
+    hi[w] = pack2(xh, yh);
+    lo[w] = pack2(xl, yl);
   }
-  __device__ void pad(const MeasureArgs& a, int lane) {
-    for (int k = 2 * a.chi_r + lane; k < a.ld_out; k += 64) {
-      hi[k] = (bf16_t)0.f;
-      lo[k] = (bf16_t)0.f;
+  __device__ void pad(const MeasureProb& a, int lane) {
+    for (int k = 2 * a.chi_r + 2 * lane; k < ld; k += 128) {
+      const size_t w = kblk_off(row, k, ld) >> 1;
+      hi[w] = 0u;
+      lo[w] = 0u;
     }
+  }
+  static __device__ uint32_t pack2(bf16_t a, bf16_t b) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
   }
 };
 
 template <>
 struct LWriter<kOutF16> {
-  f16_t* hi;
-  __device__ LWriter(const MeasureArgs& a, int row) : hi((f16_t*)a.Lh + (size_t)row * a.ld_out) {}
+  uint32_t* hi;
+  size_t row;
+  int ld;
+  __device__ LWriter(const MeasureProb& a, int r) : hi((uint32_t*)a.Lh), row((size_t)r), ld(a.ld_out) {}
   __device__ void put(int r, float x, float y) {
-    hi[2 * r] = (f16_t)x;
-    hi[2 * r + 1] = (f16_t)y;
+    const f16_t xh = (f16_t)x, yh = (f16_t)y;
+    hi[kblk_off(row, 2 * r, ld) >> 1] =
+        (uint32_t)__builtin_bit_cast(uint16_t, xh) | ((uint32_t)__builtin_bit_cast(uint16_t, yh) << 16);
   }
-  __device__ void pad(const MeasureArgs& a, int lane) {
-    for (int k = 2 * a.chi_r + lane; k < a.ld_out; k += 64) hi[k] = (f16_t)0.f;
+  __device__ void pad(const MeasureProb& a, int lane) {
+    for (int k = 2 * a.chi_r + 2 * lane; k < ld; k += 128) hi[kblk_off(row, k, ld) >> 1] = 0u;
   }
 };
 
+// k! for k < 16 (exact in FP64).
+__constant__ double kFact[DMAX] = {1.0, 1.0, 2.0, 6.0, 24.0, 120.0, 720.0, 5040.0, 40320.0, 362880.0, 3628800.0,
+                                   39916800.0, 479001600.0, 6227020800.0, 87178291200.0, 1307674368000.0};
+
+// Entry (i, j) of the displacement operator on a d-level Fock space (Eq. 7):
+// D = e^{-|mu|^2/2} e^{mu a^+} e^{-mu^* a}.  The first factor is lower
+// triangular with entries mu^{i-k} sqrt(i!/k!)/(i-k)!, the second upper
+// triangular with entries (-mu^*)^{j-k} sqrt(j!/k!)/(j-k)!, so
+// D_ij = e^{-|mu|^2/2} sum_{k <= min(i,j)} mu^{i-k} (-mu^*)^{j-k} sqrt(i! j!) / (k! (i-k)! (j-k)!).
+__device__ inline float2 displacement_entry(double mr, double mi, int i, int j) {
+  double sr = 0.0, si = 0.0;
+  const int kmax = i < j ? i : j;
+  for (int k = 0; k <= kmax; ++k) {
+    // mu^{i-k}
+    double pr = 1.0, pi = 0.0;
+    for (int t = 0; t < i - k; ++t) {
+      const double nr = pr * mr - pi * mi, ni = pr * mi + pi * mr;
+      pr = nr;
+      pi = ni;
+    }
+    // (-mu^*)^{j-k} = (-mr + i mi)^{j-k}
+    for (int t = 0; t < j - k; ++t) {
+      const double nr = pr * (-mr) - pi * mi, ni = pr * mi + pi * (-mr);
+      pr = nr;
+      pi = ni;
+    }
+    const double c = sqrt(kFact[i] * kFact[j]) / (kFact[k] * kFact[i - k] * kFact[j - k]);
+    sr += c * pr;
+    si += c * pi;
+  }
+  const double g = exp(-0.5 * (mr * mr + mi * mi));
+  return make_float2((float)(g * sr), (float)(g * si));
+}
+
 template <int OUT>
-__global__ __launch_bounds__(256) void measure_kernel(MeasureArgs a) {
+__global__ __launch_bounds__(256) void measure_kernel(const MeasureProb* probs, const ChunkArgs* chp, uint64_t seed,
+                                                      int* nflag) {
+  __shared__ float2 Dsh[4][DMAX * DMAX];  // displacement operator of each wave's sample
+  const ChunkArgs ch = *chp;
   const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= a.rows) return;
+  const int wv = threadIdx.x >> 6;
+  const int row = blockIdx.x * 4 + wv;
+  if (row >= ch.rows) return;
+  const MeasureProb a = probs[blockIdx.y];
+  const int64_t crow = ch.c0 + row;  // row within the call
+  double* const logp = a.logp + (a.logp_in_call ? crow : row);
   const int d = a.d, T = a.T;
-  const float* qp = a.qpart + (size_t)row * (d * T);
+  const bool disp = a.mu != nullptr;
+  const float2* Wrow = a.W + (size_t)row * d * a.chi_r;
 
   double q[DMAX], P[DMAX];
+  if (!disp) {
+    // branch weights from the contraction's partial sums
+    const float* qp = a.qpart + (size_t)row * (d * T);
+#pragma unroll
+    for (int i = 0; i < DMAX; ++i) {
+      double qi = 0.0;
+      if (i < d)
+        for (int t = 0; t < T; ++t) qi += (double)qp[i * T + t];
+      q[i] = qi;
+    }
+  } else {
+    // W' = D(mu) W over the physical index; weights of W' summed per lane in
+    // FP32 over its columns r, then across lanes in FP64 (fixed butterfly).
+    const float2 m = a.mu[(size_t)crow * a.M + a.site];
+    for (int t = lane; t < d * d; t += 64) Dsh[wv][t] = displacement_entry(m.x, m.y, t / d, t % d);
+    __builtin_amdgcn_wave_barrier();
+    const float2* D = Dsh[wv];
+    float qa[DMAX];
+#pragma unroll
+    for (int i = 0; i < DMAX; ++i) qa[i] = 0.f;
+    for (int r = lane; r < a.chi_r; r += 64) {
+      float2 w[DMAX];
+#pragma unroll
+      for (int jj = 0; jj < DMAX; ++jj) w[jj] = jj < d ? Wrow[(size_t)jj * a.chi_r + r] : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int i = 0; i < DMAX; ++i) {
+        if (i < d) {
+          float xr = 0.f, xi = 0.f;
+#pragma unroll
+          for (int jj = 0; jj < DMAX; ++jj) {
+            if (jj < d) {
+              const float2 g = D[i * d + jj];
+              xr += g.x * w[jj].x - g.y * w[jj].y;
+              xi += g.x * w[jj].y + g.y * w[jj].x;
+            }
+          }
+          qa[i] += xr * xr + xi * xi;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < DMAX; ++i) {
+      double v = (double)qa[i];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      q[i] = i < d ? v : 0.0;
+    }
+  }
   double acc = 0.0;
 #pragma unroll
   for (int i = 0; i < DMAX; ++i) {
-    double qi = 0.0;
-    if (i < d)
-      for (int t = 0; t < T; ++t) qi += (double)qp[i * T + t];
-    q[i] = qi;
-    acc += qi;  // left-to-right prefix sums
+    acc += q[i];  // left-to-right prefix sums
     P[i] = acc;
   }
   double S = 0.0;
@@ -128,12 +231,12 @@ __global__ __launch_bounds__(256) void measure_kernel(MeasureArgs a) {
   for (int i = 0; i < DMAX; ++i)
     if (i == d - 1) S = P[i];
 
-  const double lp_prev = a.logp[row];
+  const double lp_prev = *logp;
   const bool alive = !(lp_prev == -INFINITY);
   bool ok = alive && isfinite(S) && S > 0.0;
 
-  const uint64_t n = (uint64_t)(a.n0 + row);
-  const uint64_t x = philox_word0(n, (uint64_t)a.site, a.seed, a.mps_id);
+  const uint64_t n = (uint64_t)(ch.n_offset + crow);
+  const uint64_t x = philox_word0(n, (uint64_t)a.site, seed, a.mps_id);
   const double u = ((double)(x >> 12) + 0.5) * 0x1p-52;
 
   int s = 0;
@@ -149,13 +252,13 @@ __global__ __launch_bounds__(256) void measure_kernel(MeasureArgs a) {
   if (!ok) s = 0;
 
   if (lane == 0) {
-    a.outcomes[(size_t)row * a.M + a.site] = ok ? s : -1;
-    a.logp[row] = ok ? lp_prev + (log(qs) - log(S)) : -INFINITY;
-    if (alive && !ok) atomicAdd(a.nflag, 1);
-    if (row < a.emit_rows) {
-      if (a.emit_u) a.emit_u[(size_t)row * a.M + a.site] = u;
+    a.outcomes[(size_t)crow * a.M + a.site] = ok ? s : -1;
+    *logp = ok ? lp_prev + (log(qs) - log(S)) : -INFINITY;
+    if (alive && !ok) atomicAdd(nflag, 1);
+    if (crow < a.emit_n) {
+      if (a.emit_u) a.emit_u[(size_t)crow * a.M + a.site] = u;
       if (a.emit_probs) {
-        double* ep = a.emit_probs + ((size_t)row * a.M + a.site) * a.emit_dmax;
+        double* ep = a.emit_probs + ((size_t)crow * a.M + a.site) * a.emit_dmax;
 #pragma unroll
         for (int i = 0; i < DMAX; ++i)
           if (i < d && i < a.emit_dmax) ep[i] = ok ? q[i] / S : NAN;
@@ -163,13 +266,26 @@ __global__ __launch_bounds__(256) void measure_kernel(MeasureArgs a) {
     }
   }
 
-  const float2* src = a.W + (size_t)row * d * a.chi_r + (size_t)s * a.chi_r;
+  const float2* src = Wrow + (size_t)s * a.chi_r;
   LWriter<OUT> out(a, row);
-  if (ok) {
+  if (ok && !disp) {
     const float scale = (float)(1.0 / sqrt(qs));
     for (int r = lane; r < a.chi_r; r += 64) {
       const float2 w = src[r];
       out.put(r, w.x * scale, w.y * scale);
+    }
+  } else if (ok) {
+    // chosen branch of W' = D(mu) W
+    const float scale = (float)(1.0 / sqrt(qs));
+    const float2* Ds = Dsh[wv] + s * d;
+    for (int r = lane; r < a.chi_r; r += 64) {
+      float xr = 0.f, xi = 0.f;
+      for (int jj = 0; jj < d; ++jj) {
+        const float2 g = Ds[jj], w = Wrow[(size_t)jj * a.chi_r + r];
+        xr += g.x * w.x - g.y * w.y;
+        xi += g.x * w.y + g.y * w.x;
+      }
+      out.put(r, xr * scale, xi * scale);
     }
   } else {
     for (int r = lane; r < a.chi_r; r += 64) out.put(r, 0.f, 0.f);
@@ -177,23 +293,29 @@ __global__ __launch_bounds__(256) void measure_kernel(MeasureArgs a) {
   out.pad(a, lane);
 }
 
-__global__ void init_kernel(float2* L, double* logp, int rows) {
+// chi_0 = 1 (the open left end): every left vector is [1].  FP32: one
+// complex per row; 16-bit: (1, 0) followed by zero padding up to ld.
+__global__ void init_kernel(const InitProb* probs, const ChunkArgs* chp) {
+  const ChunkArgs ch = *chp;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < rows) {
-    L[i] = make_float2(1.f, 0.f);  // chi_0 = 1: the open left end
-    logp[i] = 0.0;
+  const InitProb a = probs[blockIdx.y];
+  if (i < ch.rows) {
+    ((float2*)a.L)[i] = make_float2(1.f, 0.f);
+    a.logp[a.logp_in_call ? ch.c0 + i : i] = 0.0;
   }
 }
 
-// 16-bit left vectors for chi_0 = 1: (1, 0) followed by zero padding up to ld.
 template <typename T>
-__global__ void init_lp_kernel(T* Lh, T* Ll, int ld, double* logp, int rows) {
+__global__ void init_lp_kernel(const InitProb* probs, const ChunkArgs* chp) {
+  const ChunkArgs ch = *chp;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < rows * ld) {
-    const int r = i / ld, k = i - r * ld;
-    Lh[i] = (T)(k == 0 ? 1.f : 0.f);
-    if (Ll) Ll[i] = (T)0.f;
-    if (k == 0) logp[r] = 0.0;
+  const InitProb a = probs[blockIdx.y];
+  if (i < ch.rows * a.ld) {
+    const int r = i / a.ld, k = i - r * a.ld;
+    const size_t off = kblk_off((size_t)r, k, a.ld);
+    ((T*)a.L)[off] = (T)(k == 0 ? 1.f : 0.f);
+    if (a.Ll) ((T*)a.Ll)[off] = (T)0.f;
+    if (k == 0) a.logp[a.logp_in_call ? ch.c0 + r : r] = 0.0;
   }
 }
 
@@ -204,20 +326,20 @@ __global__ void zero_int_kernel(int* p, int n) {
 
 }  // namespace
 
-hipError_t launch_init(float2* L, double* logp, int rows, hipStream_t s) {
-  if (rows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(init_kernel, dim3((rows + 255) / 256), dim3(256), 0, s, L, logp, rows);
-  return hipGetLastError();
-}
-
-hipError_t launch_init_lp(int form, void* Lh, void* Ll, int ld, double* logp, int rows, hipStream_t s) {
-  if (rows <= 0) return hipSuccess;
-  const long long n = (long long)rows * ld;
-  const dim3 grid((unsigned)((n + 255) / 256));
-  if (form == kBf16x3)
-    hipLaunchKernelGGL(init_lp_kernel<bf16_t>, grid, dim3(256), 0, s, (bf16_t*)Lh, (bf16_t*)Ll, ld, logp, rows);
-  else
-    hipLaunchKernelGGL(init_lp_kernel<f16_t>, grid, dim3(256), 0, s, (f16_t*)Lh, (f16_t*)nullptr, ld, logp, rows);
+hipError_t launch_init(int form, const InitProb* probs, int nprob, const ChunkArgs* ch, int grid_rows,
+                       hipStream_t s) {
+  if (grid_rows <= 0 || nprob <= 0) return hipSuccess;
+  if (form == 0) {
+    hipLaunchKernelGGL(init_kernel, dim3((grid_rows + 255) / 256, nprob), dim3(256), 0, s, probs, ch);
+  } else {
+    // every problem of a launch shares ld = padded K of chi_0 = 1
+    const long long n = (long long)grid_rows * lp_pad_k(1);
+    const dim3 grid((unsigned)((n + 255) / 256), nprob);
+    if (form == kBf16x3)
+      hipLaunchKernelGGL(init_lp_kernel<bf16_t>, grid, dim3(256), 0, s, probs, ch);
+    else
+      hipLaunchKernelGGL(init_lp_kernel<f16_t>, grid, dim3(256), 0, s, probs, ch);
+  }
   return hipGetLastError();
 }
 
@@ -227,18 +349,16 @@ hipError_t launch_zero_int(int* p, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_measure(const MeasureArgs& a, hipStream_t s) {
-  if (a.rows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(measure_kernel<kOutF32>, dim3((a.rows + 3) / 4), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_measure_lp(int form, const MeasureArgs& a, hipStream_t s) {
-  if (a.rows <= 0) return hipSuccess;
-  if (form == kBf16x3)
-    hipLaunchKernelGGL(measure_kernel<kOutBf16x2>, dim3((a.rows + 3) / 4), dim3(256), 0, s, a);
+hipError_t launch_measure(int form, const MeasureProb* probs, int nprob, const ChunkArgs* ch, int grid_rows,
+                          uint64_t seed, int* nflag, hipStream_t s) {
+  if (grid_rows <= 0 || nprob <= 0) return hipSuccess;
+  const dim3 grid((grid_rows + 3) / 4, nprob);
+  if (form == 0)
+    hipLaunchKernelGGL(measure_kernel<kOutF32>, grid, dim3(256), 0, s, probs, ch, seed, nflag);
+  else if (form == kBf16x3)
+    hipLaunchKernelGGL(measure_kernel<kOutBf16x2>, grid, dim3(256), 0, s, probs, ch, seed, nflag);
   else
-    hipLaunchKernelGGL(measure_kernel<kOutF16>, dim3((a.rows + 3) / 4), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(measure_kernel<kOutF16>, grid, dim3(256), 0, s, probs, ch, seed, nflag);
   return hipGetLastError();
 }
 

@@ -1,5 +1,12 @@
-// Internal interface between the C ABI (mps_abi.cpp) and the HIP kernels
-// (sweep_kernels.hip).  Not installed; the public interface is include/mps.h.
+// Internal interface between the C ABI (mps_abi.cpp) and the HIP kernels.
+// Not installed; the public interface is include/mps.h.
+//
+// Every launch works on a group of problems (one problem = one chain at one
+// site).  A single chain is a group of one; a batch of chains advances all
+// chains that have a site k in the same launches.  Problem tables are
+// chunk-invariant and live in device memory (uploaded once per call); what
+// changes from chunk to chunk (row count, first sample index) is passed in
+// ChunkArgs.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -7,90 +14,110 @@
 
 namespace mps {
 
-// Tile of the FP32 contraction: BM samples x BNC complex columns of one
-// physical branch, K stepped BK complex values at a time.
+// ---- FP32 contraction tile: BM samples x BNC complex columns of one branch,
+// K stepped BK complex values at a time.
 constexpr int kBM = 128;
 constexpr int kBNC = 64;
 constexpr int kBK = 16;
-
-// Column tiles per branch for a right bond chi_r.
 __host__ __device__ inline int col_tiles(int chi_r) { return (chi_r + kBNC - 1) / kBNC; }
 
-struct ContractArgs {
-  const float2* L;   // [rows][K] complex, row pitch K
-  const float2* A;   // [K][d][chi_r] complex (the site tensor)
-  float2* W;         // [rows][d*chi_r] complex
-  float* qpart;      // [rows][d*T] partial branch weights, T = col_tiles(chi_r)
-  int rows;
-  int K;
-  int d;
-  int chi_r;
-};
-
-// Low-precision contraction (16-bit MFMA operands, FP32 accumulate).  Tiles:
-// kLpBM samples x kLpBNC complex columns of one branch; K in steps of kLpBK
-// real values.  The packed site tensor pads every branch to a multiple of
-// kLpBNC columns and K to a multiple of kLpKA real values, with zeros.
+// ---- 16-bit contraction tile: kLpBM samples x kLpBNC complex columns of one
+// branch; K in stages of kLpBK real values.  The packed site tensor pads
+// every branch to a multiple of kLpBNC columns and K to a multiple of kLpKA
+// real values, with zeros.
 constexpr int kLpBM = 256;
 constexpr int kLpBNC = 128;
-constexpr int kLpBK = 32;
+constexpr int kLpBK = 16;
 constexpr int kLpKA = 64;
 __host__ __device__ inline int lp_pad_cols(int chi_r) { return (chi_r + kLpBNC - 1) / kLpBNC * kLpBNC; }
 __host__ __device__ inline int lp_pad_k(int chi) { return (2 * chi + kLpKA - 1) / kLpKA * kLpKA; }
 
+// Both 16-bit operands (left vectors, packed site tensor) are stored K-blocked:
+// a matrix of R rows (a multiple of 256) and Kp columns (a multiple of 16) is
+// a grid of 256 x 16 tiles, each tile 8 KiB contiguous with its rows 32 bytes
+// apart, tiles of one row block consecutive in K.  One pipeline stage of the
+// contraction is then one contiguous 8 KiB block per operand, which the
+// loads stream as whole cache lines.
+__host__ __device__ inline size_t kblk_off(size_t r, int k, int Kp) {
+  return ((r >> 8) * (size_t)(Kp >> 4) + (size_t)(k >> 4)) * 4096 + (r & 255) * 16 + (k & 15);
+}
+
 enum LpForm { kBf16x3 = 1, kFp16 = 2 };
 
-struct PackArgs {
+// Per-chunk arguments live in device memory (the "current chunk" slot), so
+// that one captured graph of a chunk's launches can be replayed for every
+// chunk; the launch grids are sized for grid_rows >= rows.
+struct ChunkArgs {
+  int rows;          // samples in this chunk (the same for every chain)
+  int pad_;
+  int64_t c0;        // first row of the chunk within the call
+  int64_t n_offset;  // global index of row 0 of the call
+};
+
+struct ContractProb {
+  const float2* L;   // [rows][K] complex, row pitch K
+  const float2* A;   // [K][d][chi_r] complex (the site tensor)
+  float2* W;         // [rows][d*chi_r] complex
+  float* qpart;      // [rows][d*T] partial branch weights, T = col_tiles(chi_r)
+  int K, d, chi_r;
+};
+
+struct PackProb {
   const float2* A;   // [K][d][chi_r] complex site tensor
-  void* Bh;          // [d*CP*2][Kp] 16-bit, the real embedding, K contiguous
-  void* Bl;          // same, low parts (bf16x3 only)
+  void* Bh;          // [d*CP*2][Kp] 16-bit real embedding, K contiguous
+  void* Bl;          // low parts (bf16x3 only)
   int K, d, chi_r, CP, Kp;
 };
 
-struct ContractLpArgs {
+struct ContractLpProb {
   const void* Lh;    // [rows_alloc][Kp] 16-bit left vectors (interleaved re, im), K padded with 0
   const void* Ll;    // low parts (bf16x3 only)
   const void* Bh;    // packed site tensor
   const void* Bl;
   float2* W;         // [rows][d*chi_r] complex FP32
   float* qpart;      // [rows][d*T], T = CP / kLpBNC
-  int rows, Kp, d, chi_r, CP;
+  int Kp, d, chi_r, CP;
 };
 
-struct MeasureArgs {
+struct MeasureProb {
   const float2* W;       // [rows][d*chi_r]
   const float* qpart;    // [rows][d*T]
   float2* Lout;          // [rows][chi_r]  (FP32 path)
   void* Lh;              // [rows][ld_out] 16-bit outputs (low-precision paths)
   void* Ll;
   int ld_out;            // padded row length of Lh/Ll in 16-bit elements
-  int rows;
-  int d;
-  int chi_r;
-  int T;
+  int d, chi_r, T;
   int site;              // k
   int M;                 // sites in the chain (row pitch of outcomes)
-  int64_t n0;            // global index of row 0
-  uint64_t seed;
   uint64_t mps_id;
-  int32_t* outcomes;     // [rows][M] slice starting at row 0 of this chunk
-  double* logp;          // [rows]
-  int* nflag;            // count of samples flagged at this call
-  int64_t emit_rows;     // rows [0, emit_rows) of this chunk emit
+  int32_t* outcomes;     // [N][M] of the call (row c0 + r of chunk row r)
+  double* logp;          // caller's [N] (indexed c0 + r) or chain scratch [rows] (indexed r)
+  int logp_in_call;      // 1: logp is the caller's buffer
   int emit_dmax;
-  double* emit_probs;    // [..][M][emit_dmax], already offset to row 0 of the chunk
-  double* emit_u;        // [..][M]
+  int64_t emit_n;        // rows [0, emit_n) of the call emit
+  double* emit_probs;    // [emit_n][M][emit_dmax]
+  double* emit_u;        // [emit_n][M]
+  const float2* mu;      // displacement per (call row, site) [N][M], or NULL
 };
 
-hipError_t launch_init(float2* L, double* logp, int rows, hipStream_t s);
-hipError_t launch_zero_int(int* p, int n, hipStream_t s);
-hipError_t launch_contract_f32(const ContractArgs& a, hipStream_t s);
-hipError_t launch_measure(const MeasureArgs& a, hipStream_t s);
+struct InitProb {
+  void* L;               // FP32: float2 [rows]; 16-bit: Lh [rows][ld]
+  void* Ll;              // 16-bit low parts or NULL
+  int ld;                // 16-bit row length (padded K of chi_0 = 1)
+  double* logp;          // as in MeasureProb
+  int logp_in_call;
+};
 
-// Low-precision path (form = kBf16x3 or kFp16).
-hipError_t launch_init_lp(int form, void* Lh, void* Ll, int ld, double* logp, int rows, hipStream_t s);
-hipError_t launch_pack_lp(int form, const PackArgs& a, hipStream_t s);
-hipError_t launch_contract_lp(int form, const ContractLpArgs& a, hipStream_t s);
-hipError_t launch_measure_lp(int form, const MeasureArgs& a, hipStream_t s);
+hipError_t launch_zero_int(int* p, int n, hipStream_t s);
+// form: 0 = FP32 path, kBf16x3, kFp16
+hipError_t launch_init(int form, const InitProb* probs, int nprob, const ChunkArgs* ch, int grid_rows, hipStream_t s);
+hipError_t launch_contract_f32(const ContractProb* probs, const int* tn_start, int nprob, int tn_total,
+                               const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s);
+hipError_t launch_pack_lp(int form, const PackProb* probs, const int* blk_start, int nprob, int blk_total,
+                          hipStream_t s);
+hipError_t launch_contract_lp(int form, const ContractLpProb* probs, const int* tn_start, int nprob, int tn_total,
+                              const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s);
+hipError_t launch_measure(int form, const MeasureProb* probs, int nprob, const ChunkArgs* ch, int grid_rows,
+                          uint64_t seed, int* nflag, hipStream_t s);
 
 }  // namespace mps

@@ -23,7 +23,7 @@ MPS_C64 = 0
 STATUS_NAMES = {0: "MPS_OK", -1: "MPS_EINVAL", -2: "MPS_ENOMEM", -3: "MPS_ENODEV",
                 -4: "MPS_EHIP", -5: "MPS_ENUMERIC"}
 
-EXPORTS = ("mps_options_init", "mps_create", "mps_set_options", "mps_sample",
+EXPORTS = ("mps_options_init", "mps_create", "mps_set_options", "mps_sample", "mps_sample_batch",
            "mps_get_stats", "mps_last_error", "mps_destroy")
 
 
@@ -37,9 +37,25 @@ class mps_options(ctypes.Structure):
         ("mps_id", ctypes.c_uint64),
         ("emit_n", ctypes.c_int64),
         ("emit_dmax", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("tile_group", ctypes.c_int32),
         ("emit_probs", ctypes.c_void_p),
         ("emit_u", ctypes.c_void_p),
+        ("graph", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("displace", ctypes.c_void_p),
+    ]
+
+
+class mps_chain(ctypes.Structure):
+    _fields_ = [
+        ("tensors", ctypes.POINTER(ctypes.c_void_p)),
+        ("chi", ctypes.POINTER(ctypes.c_int32)),
+        ("d", ctypes.POINTER(ctypes.c_int32)),
+        ("M", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("mps_id", ctypes.c_uint64),
+        ("outcomes", ctypes.c_void_p),
+        ("logp", ctypes.c_void_p),
     ]
 
 
@@ -87,6 +103,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_int64,
                                ctypes.c_int64, ctypes.c_uint64, P, P]
     lib.mps_sample.restype = ctypes.c_int
+    lib.mps_sample_batch.argtypes = [P, ctypes.c_int32, ctypes.POINTER(mps_chain), ctypes.c_int32, ctypes.c_int64,
+                                     ctypes.c_int64, ctypes.c_uint64]
+    lib.mps_sample_batch.restype = ctypes.c_int
     lib.mps_get_stats.argtypes = [P, ctypes.POINTER(mps_stats)]
     lib.mps_get_stats.restype = ctypes.c_int
     lib.mps_last_error.argtypes = []
@@ -136,6 +155,24 @@ def mps_sample(h, tensor_ptrs, dtype: int, chi, d, M: int, N: int, n_offset: int
                              ctypes.c_void_p(logp_ptr) if logp_ptr else None)
 
 
+def make_chain(tensor_ptrs, chi, d, mps_id: int, outcomes_ptr: int, logp_ptr: int | None):
+    """An mps_chain; the returned tuple keeps the ctypes arrays alive."""
+    M = len(tensor_ptrs)
+    arr = (ctypes.c_void_p * M)(*[ctypes.c_void_p(int(p)) if p else None for p in tensor_ptrs])
+    chi_a = (ctypes.c_int32 * len(chi))(*[int(x) for x in chi])
+    d_a = (ctypes.c_int32 * len(d))(*[int(x) for x in d])
+    c = mps_chain(ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p)), ctypes.cast(chi_a, ctypes.POINTER(ctypes.c_int32)),
+                  ctypes.cast(d_a, ctypes.POINTER(ctypes.c_int32)), M, 0, mps_id, outcomes_ptr or None,
+                  logp_ptr or None)
+    return c, (arr, chi_a, d_a)
+
+
+def mps_sample_batch(h, chains, dtype: int, N: int, n_offset: int, seed: int) -> int:
+    """Raw call over a list of mps_chain; returns the status code."""
+    arr = (mps_chain * len(chains))(*chains)
+    return load().mps_sample_batch(h, len(chains), arr, dtype, N, n_offset, ctypes.c_uint64(seed))
+
+
 def mps_get_stats(h) -> mps_stats:
     st = mps_stats()
     rc = load().mps_get_stats(h, ctypes.byref(st))
@@ -158,10 +195,13 @@ class Sampler:
     """
 
     def __init__(self, device: int = 0, n_chunk: int = 0, profile: bool = False,
-                 max_device_bytes: int = 0, mps_id: int = 0, precision=MPS_FP32):
+                 max_device_bytes: int = 0, mps_id: int = 0, precision=MPS_FP32, tile_group: int = 0,
+                 graph: bool = False):
         if isinstance(precision, str):
             precision = PRECISIONS[precision]
         self.opt = mps_options_init()
+        self.opt.tile_group = tile_group
+        self.opt.graph = int(graph)
         self.opt.n_chunk = n_chunk
         self.opt.profile = int(profile)
         self.opt.max_device_bytes = max_device_bytes
@@ -182,7 +222,9 @@ class Sampler:
             pass
 
     def sample(self, tensors, N: int, seed: int, n_offset: int = 0, emit_n: int = 0,
-               emit_dmax: int = 0, want_logp: bool = True, stream=None, raise_numeric: bool = False):
+               emit_dmax: int = 0, want_logp: bool = True, stream=None, raise_numeric: bool = False,
+               displace=None):
+        """displace: optional complex64 CUDA tensor [N, M] of per-sample displacements."""
         import torch
         dev = torch.device("cuda", self.device)
         M = len(tensors)
@@ -203,6 +245,11 @@ class Sampler:
             opt.emit_dmax = emit_dmax
             opt.emit_probs = emit_probs.data_ptr()
             opt.emit_u = emit_u.data_ptr()
+        if displace is not None:
+            if displace.dtype != torch.complex64 or not displace.is_cuda or tuple(displace.shape) != (N, M) \
+                    or not displace.is_contiguous():
+                raise ValueError("displace must be a contiguous complex64 CUDA tensor of shape (N, M)")
+            opt.displace = displace.data_ptr()
         s = stream if stream is not None else torch.cuda.current_stream(dev)
         opt.stream = s.cuda_stream
         mps_set_options(self.h, opt)
@@ -217,3 +264,37 @@ class Sampler:
             out["probs"] = emit_probs
             out["u"] = emit_u
         return out
+
+    def sample_batch(self, chains, N: int, seed: int, n_offset: int = 0, want_logp: bool = True, stream=None,
+                     raise_numeric: bool = False):
+        """chains: list of lists of complex64 CUDA tensors; chain b uses mps_id = b.
+
+        Returns a list of (outcomes [N, M_b] int32, logp [N] float64) CUDA tensor pairs.
+        """
+        import torch
+        dev = torch.device("cuda", self.device)
+        outs, keep, descs = [], [], []
+        for b, tensors in enumerate(chains):
+            for t in tensors:
+                if t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous():
+                    raise ValueError("site tensors must be contiguous complex64 CUDA tensors")
+            M = len(tensors)
+            chi = [int(tensors[0].shape[0])] + [int(t.shape[2]) for t in tensors]
+            d = [int(t.shape[1]) for t in tensors]
+            o = torch.empty((N, M), dtype=torch.int32, device=dev)
+            lp = torch.empty((N,), dtype=torch.float64, device=dev) if want_logp else None
+            c, k = make_chain([t.data_ptr() for t in tensors], chi, d, b, o.data_ptr(),
+                              lp.data_ptr() if lp is not None else None)
+            descs.append(c)
+            keep.append(k)
+            outs.append((o, lp))
+        opt = mps_options.from_buffer_copy(self.opt)
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        opt.stream = s.cuda_stream
+        mps_set_options(self.h, opt)
+        rc = mps_sample_batch(self.h, descs, MPS_C64, N, n_offset, seed)
+        self.status = rc
+        if rc and (rc != MPS_ENUMERIC or raise_numeric):
+            raise MPSError(rc, mps_last_error())
+        self.stats = mps_get_stats(self.h)
+        return outs

@@ -35,7 +35,7 @@ def upload(tensors_c64, device="cuda"):
     return out
 
 
-def compare(tensors_c64, seed, gpu, rows=None, n_offset=0, eps=EPS_FP32, mps_id=0, n_index=None):
+def compare(tensors_c64, seed, gpu, rows=None, n_offset=0, eps=EPS_FP32, mps_id=0, n_index=None, displace=None):
     """Forced-prefix comparison of a GPU result dict with the oracle.
 
     gpu: dict with numpy 'outcomes' [N, M], 'logp' [N], optional 'probs'
@@ -52,7 +52,8 @@ def compare(tensors_c64, seed, gpu, rows=None, n_offset=0, eps=EPS_FP32, mps_id=
     t128 = synth.promote(tensors_c64)
     if n_index is None:
         n_index = n_offset + rows
-    f = oracle.forced_probs(t128, outc[rows], seed, mps_id=mps_id, n_index=np.asarray(n_index))
+    disp = None if displace is None else np.asarray(displace, dtype=np.complex128)[rows]
+    f = oracle.forced_probs(t128, outc[rows], seed, mps_id=mps_id, n_index=np.asarray(n_index), displace=disp)
     d = np.array([t.shape[1] for t in tensors_c64])
     rep = {"rows": int(len(rows)), "sites": int(M)}
 

@@ -38,7 +38,7 @@ def test_exports_every_declared_symbol(lib):
 
 def test_options_struct_matches_header():
     # the binding's struct must have the header's size (8-byte aligned fields)
-    assert ctypes.sizeof(mps.mps_options) == 4 + 4 + 8 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8
+    assert ctypes.sizeof(mps.mps_options) == 4 + 4 + 8 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8 + 4 + 4 + 8
     assert ctypes.sizeof(mps.mps_stats) == 11 * 8
 
 
@@ -125,5 +125,21 @@ def test_memory_cap_reports_enomem_before_device():
     try:
         rc = _call(h, chi=[1, 16, 256, 16, 1], d=[16, 16, 16, 16], M=4, tensors=[1, 1, 1, 1])
         assert rc == mps.MPS_ENOMEM, (rc, mps.mps_last_error())
+    finally:
+        mps.mps_destroy(h)
+
+
+def test_batch_validation_on_host():
+    h = mps.mps_create(0)
+    try:
+        good, keep1 = mps.make_chain([1, 1], [1, 4, 1], [4, 4], 0, 1, None)
+        bad, keep2 = mps.make_chain([1, 1], [2, 4, 1], [4, 4], 1, 1, None)  # chi[0] != 1
+        assert mps.mps_sample_batch(h, [good, bad], mps.MPS_C64, 10, 0, 1) == mps.MPS_EINVAL
+        assert "chain 1" in mps.mps_last_error()
+        nul, keep3 = mps.make_chain([1, 1], [1, 4, 1], [4, 4], 2, 0, None)  # outcomes NULL
+        assert mps.mps_sample_batch(h, [good, nul], mps.MPS_C64, 10, 0, 1) == mps.MPS_EINVAL
+        assert mps.load().mps_sample_batch(h, 0, None, mps.MPS_C64, 10, 0, 1) == mps.MPS_EINVAL
+        assert mps.mps_sample_batch(h, [good], 9, 10, 0, 1) == mps.MPS_EINVAL  # dtype
+        assert mps.mps_sample_batch(h, [good], mps.MPS_C64, 0, 0, 1) == mps.MPS_OK  # empty
     finally:
         mps.mps_destroy(h)
