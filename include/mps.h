@@ -27,7 +27,8 @@
  * Status codes: every entry point returns MPS_OK or a negative code;
  * mps_last_error() gives a message for the calling thread.  Argument
  * checks run on the host before any HIP call, so MPS_EINVAL is reported
- * the same way on a machine without a GPU.
+ * the same way on a machine without a GPU; only where a site pointer lives
+ * (device, pinned host, or neither) is checked after the device is set.
  */
 #ifndef MPS_SAMPLE_H
 #define MPS_SAMPLE_H
@@ -59,9 +60,30 @@ enum {
                         renormalised per sample (entries within [-1, 1])           */
 };
 
-/* Element type of the site tensors. */
+/* Storage of the site tensors (Section 3.3.2: tensors stored and moved in
+ * low precision, converted before the contraction).  Site k holds the complex
+ * tensor [chi[k]][d[k]][chi[k+1]] row-major as:
+ *   MPS_C64   (re, im) float pairs, interleaved (8 bytes per entry);
+ *   MPS_CF16  (re, im) IEEE binary16 pairs (4 bytes per entry);
+ *   MPS_CF8   (re, im) OCP FP8 E4M3 code pairs (2 bytes per entry), then, at
+ *             the next multiple of 256 bytes, one float scale per 128 x 128
+ *             block of the chi[k] x d[k]*chi[k+1] complex matrix, row-major
+ *             over blocks; an entry is its code's value times its block's
+ *             scale.
+ * A site pointer may be device memory or pinned host memory (hipHostMalloc);
+ * pageable host memory is rejected (MPS_EINVAL).  Host sites are copied to
+ * the device on a side stream of the handle, one site ahead of the compute
+ * stream (two copy slots), and every stored form other than device MPS_C64
+ * is expanded to complex64 on the device (two expansion slots) right before
+ * its site is contracted.  A call with such "staged" sites visits each site
+ * once for all its chunks, so every chunk keeps its own left-vector state
+ * and the scratch grows with N (about N * chi_max * 8 bytes).  The staging
+ * slots are held by the handle: 2 * (largest expanded site) + 2 * (largest
+ * stored host site) bytes, counted against max_device_bytes.             */
 enum {
-  MPS_C64 = 0        /* complex64: (re, im) float pairs, interleaved              */
+  MPS_C64 = 0,
+  MPS_CF16 = 1,
+  MPS_CF8 = 2
 };
 
 typedef struct mps_ctx* mps_handle;
@@ -127,6 +149,10 @@ typedef struct {
   int64_t n_chunk;            /* chunk size the last call used                      */
   int64_t flagged;            /* samples that met S <= 0 or non-finite S            */
   int64_t scratch_bytes;      /* device scratch held by the handle                  */
+  double h2d_bytes;           /* site-tensor bytes copied from host memory          */
+  double h2d_ms;              /* summed event time of those copies (profile=1)      */
+  double expand_ms;           /* summed event time of the expansion kernels         */
+  int64_t staged_sites;       /* sites expanded (and, from host memory, copied)     */
 } mps_stats;
 
 /* Fill *opt with defaults (FP32, planner chunking, null stream, no emits). */
@@ -143,9 +169,10 @@ int mps_set_options(mps_handle h, const mps_options* opt);
 /*
  * Draw N samples with global indices n_offset .. n_offset+N-1.
  *
- *   tensors   host array of M DEVICE pointers; site k points to a complex
- *             tensor [chi[k]][d[k]][chi[k+1]], row-major, of element type
- *             `dtype` (MPS_C64).  Read only.
+ *   tensors   host array of M pointers (device memory or pinned host
+ *             memory); site k points to the complex tensor
+ *             [chi[k]][d[k]][chi[k+1]] stored as `dtype` (see MPS_C64 ...).
+ *             Read only.
  *   chi       host array of M+1 bond dimensions; chi[0] must be 1 (open left
  *             end); chi[M] may exceed 1 (an open right end whose right
  *             environment is the identity).  Each chi[k] <= d[k]*chi[k+1]
@@ -183,6 +210,8 @@ int mps_sample(mps_handle h, const void* const* tensors, int32_t dtype,
  * Section 3.1 (data parallelism over samples) applied across chains; the
  * site-varying bond dimensions follow Section 3.4.2.  The handle's options
  * apply (precision, chunk, stream, cap, profile); debug emits are ignored.
+ * Batched site tensors must be device-resident MPS_C64 (dtype is checked
+ * before any HIP call, residence after the device is set).
  * Returns as mps_sample; MPS_ENUMERIC counts flagged samples over all chains.
  */
 int mps_sample_batch(mps_handle h, int32_t B, const mps_chain* chains, int32_t dtype,

@@ -210,3 +210,44 @@ def config_index(outcomes: np.ndarray, dims) -> np.ndarray:
     for k, d in enumerate(dims):
         idx = idx * d + outcomes[:, k]
     return idx
+
+
+# --------------------------------------------------------------------------
+# Decoders of the compressed storage kinds (the oracle's own code; used to
+# evaluate exactly the tensor the sampler sees).
+# --------------------------------------------------------------------------
+
+def _e4m3_value(code: np.ndarray) -> np.ndarray:
+    """OCP FP8 E4M3: sign bit, 4-bit exponent (bias 7), 3-bit mantissa;
+    exponent 0 is subnormal (m/8 * 2^-6); S.1111.111 is NaN."""
+    code = np.asarray(code, dtype=np.int64)
+    s = np.where(code & 0x80, -1.0, 1.0)
+    e = (code >> 3) & 0xF
+    m = (code & 0x7).astype(np.float64)
+    normal = (1.0 + m / 8.0) * np.exp2(e - 7.0)
+    sub = (m / 8.0) * 2.0 ** -6
+    v = s * np.where(e == 0, sub, normal)
+    return np.where((e == 0xF) & (m == 7), np.nan, v)
+
+
+def decode_site(raw: np.ndarray, shape, kind: str) -> np.ndarray:
+    """complex128 site tensor of the given shape from its stored bytes."""
+    chi_l, d, chi_r = shape
+    n = chi_l * d * chi_r
+    raw = np.asarray(raw, dtype=np.uint8)
+    if kind == "c64":
+        return raw[:8 * n].view(np.complex64).astype(np.complex128).reshape(shape)
+    if kind == "cf16":
+        ri = raw[:4 * n].view(np.float16).astype(np.float64).reshape(n, 2)
+        return (ri[:, 0] + 1j * ri[:, 1]).reshape(shape)
+    if kind == "cf8":
+        blk = 128
+        codes = raw[:2 * n].reshape(chi_l, d * chi_r, 2)
+        off = -(-2 * n // 256) * 256
+        nbr, nbc = -(-chi_l // blk), -(-(d * chi_r) // blk)
+        scales = raw[off:off + 4 * nbr * nbc].view(np.float32).astype(np.float64).reshape(nbr, nbc)
+        sc = np.repeat(np.repeat(scales, blk, axis=0), blk, axis=1)[:chi_l, :d * chi_r]
+        re = _e4m3_value(codes[..., 0]) * sc
+        im = _e4m3_value(codes[..., 1]) * sc
+        return (re + 1j * im).reshape(shape)
+    raise ValueError(kind)

@@ -3,20 +3,28 @@
 // contract).
 //
 // Sweep structure (Section 3.1, Eq. 2-3): the N samples of a call are cut
-// into chunks (the paper's macro batches); each chunk walks the sites in
-// order (the dependency between sites is strict, Section 2.2).  At site k
-// one contraction and one measurement launch (plus, for the 16-bit forms,
-// one packing launch that converts the site tensor into the operand format)
+// into chunks (the paper's macro batches) and the sites are visited in order
+// (the dependency between sites is strict, Section 2.2).  At site k one
+// contraction and one measurement launch (plus, for the 16-bit forms, one
+// packing launch that converts the site tensor into the operand format)
 // advance every chain of the call that has a site k; a single chain is a
 // batch of one.  Work inside a site is data-parallel over chains, samples
 // and columns, all on one stream.
 //
-// Per chain the scratch holds one left-vector buffer (the measurement
+// Two loop orders.  With every site tensor resident in device memory as
+// complex64, each chunk walks all sites before the next chunk starts, and
+// one left-vector state is reused (the launches of a chunk can then be
+// captured once as a graph and replayed per chunk).  When site tensors are
+// held in pinned host memory or in a compressed form, the sites are the
+// outer loop instead: each tensor is copied (on a side stream, one site
+// ahead) and expanded once per call, and every chunk keeps its own state.
+//
+// Per chain the scratch holds the left-vector state (the measurement
 // overwrites the contraction's input in place: the contraction has finished
 // reading it), the site output W, the partial branch weights, and for the
 // 16-bit forms the packed site tensor.  The problem tables that the kernels
-// read (pointers and shapes per chain and site) do not depend on the chunk;
-// they are built on the host and uploaded once per call.
+// read (pointers and shapes per chain, site and state) are built on the host
+// and uploaded once per call.
 
 #include "../../include/mps.h"
 #include "sweep.h"
@@ -80,11 +88,16 @@ struct Shape {
 };
 
 struct ChainBufs {
-  size_t L = 0, Lh = 0, Ll = 0, Bh = 0, Bl = 0, W = 0, qpart = 0, logp = 0;
+  size_t L = 0, Lh = 0, Ll = 0, logp = 0;  // left-vector state (of chunk 0)
+  size_t state = 0;                        // bytes from one chunk's state to the next
+  size_t Bh = 0, Bl = 0, W = 0, qpart = 0;
 };
 
-// Per-chain scratch for `rows` samples; returns the bytes used from `off`.
-size_t chain_layout(int64_t rows, const Shape& sh, int precision, size_t off, ChainBufs& b) {
+// Per-chain scratch for `rows` samples at byte offset `off`: `nstate` copies of
+// the left-vector state (one per chunk when the chunks take turns at every
+// site, else one), then the buffers that one site's launches use and release.
+// Returns the bytes used.
+size_t chain_layout(int64_t rows, const Shape& sh, int precision, int64_t nstate, size_t off, ChainBufs& b) {
   const size_t start = off;
   auto take = [&](size_t bytes) {
     const size_t at = off;
@@ -98,12 +111,16 @@ size_t chain_layout(int64_t rows, const Shape& sh, int precision, size_t off, Ch
     const size_t ra = (size_t)((rows + mps::kLpBM - 1) / mps::kLpBM * mps::kLpBM);
     b.Lh = take(ra * sh.kpmax * 2);
     if (precision == MPS_BF16X3) b.Ll = take(ra * sh.kpmax * 2);
+  }
+  b.logp = take((size_t)rows * sizeof(double));
+  b.state = off - start;
+  off = start + b.state * (size_t)nstate;
+  if (precision != MPS_FP32) {
     b.Bh = take((size_t)sh.bmax * 2);
     if (precision == MPS_BF16X3) b.Bl = take((size_t)sh.bmax * 2);
   }
   b.W = take((size_t)rows * sh.wmax * sizeof(float2));
   b.qpart = take((size_t)rows * sh.qtmax * sizeof(float));
-  b.logp = take((size_t)rows * sizeof(double));
   return off - start;
 }
 
@@ -177,48 +194,39 @@ struct mps_ctx {
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
   int scratch_device = -1;
+  void* stage = nullptr;  // staging for stored / host-resident site tensors
+  size_t stage_bytes = 0;
+  hipStream_t side = nullptr;  // copy stream for host-resident site tensors
+  hipEvent_t ev_copy[2] = {nullptr, nullptr};
+  hipEvent_t ev_expand[2] = {nullptr, nullptr};
   std::vector<hipEvent_t> events;
   mps_stats st{};
 };
 
 namespace {
 
-int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offset, uint64_t seed, bool single) {
+int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offset, uint64_t seed, bool single,
+              int kind) {
   const mps_options& o = h->opt;
   const bool lowp = o.precision != MPS_FP32;
+  const bool split = o.precision == MPS_BF16X3;
   const int form = lowp ? lp_form(o.precision) : 0;
   const int B = (int)chains.size();
   int Mmax = 0;
   for (const Chain& c : chains) Mmax = std::max(Mmax, c.M);
 
-  // ---- plan the chunk: every chain holds scratch for nc rows ----
-  int64_t nc = o.n_chunk > 0 ? o.n_chunk : kDefaultChunk;
-  nc = std::min<int64_t>(nc, N);
-  nc = std::min<int64_t>(nc, (int64_t)1 << 30);
-  auto scratch_for = [&](int64_t rows, std::vector<ChainBufs>* bufs) {
-    size_t off = 0;
+  // A lower bound of the scratch (one sample, one state, no staging) is
+  // checked before any HIP call.
+  if (o.max_device_bytes > 0) {
+    size_t lb = 0;
     for (int b = 0; b < B; ++b) {
       ChainBufs cb;
-      off += chain_layout(rows, chains[b].sh, o.precision, off, cb);
-      if (bufs) (*bufs)[b] = cb;
+      lb += chain_layout(1, chains[b].sh, o.precision, 1, lb, cb);
     }
-    return off;
-  };
-  // problem tables: bounded by the number of (chain, site) pairs
-  size_t table_bytes = 0;
-  for (const Chain& c : chains)
-    table_bytes += (size_t)c.M * (sizeof(mps::ContractProb) + sizeof(mps::ContractLpProb) + sizeof(mps::PackProb) +
-                                  sizeof(mps::MeasureProb) + 2 * sizeof(int));
-  table_bytes += (size_t)B * sizeof(mps::InitProb) + (size_t)Mmax * 7 * 256 + 4096;
-  const size_t fixed = align_up(table_bytes) + align_up(sizeof(int));
-  if (o.max_device_bytes > 0) {
-    if ((int64_t)(fixed + scratch_for(1, nullptr)) > o.max_device_bytes)
-      return fail(MPS_ENOMEM, "scratch for one sample per chain (%zu B) exceeds max_device_bytes (%lld)",
-                  fixed + scratch_for(1, nullptr), (long long)o.max_device_bytes);
-    while (nc > 1 && (int64_t)(fixed + scratch_for(nc, nullptr)) > o.max_device_bytes) nc = (nc + 1) / 2;
+    if ((int64_t)lb > o.max_device_bytes)
+      return fail(MPS_ENOMEM, "scratch for one sample per chain (%zu B) exceeds max_device_bytes (%lld)", lb,
+                  (long long)o.max_device_bytes);
   }
-  std::vector<ChainBufs> bufs(B);
-  const size_t total = fixed + scratch_for(nc, &bufs);
 
   // ---- device ----
   int ndev = 0;
@@ -228,230 +236,432 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
   if ((e = hipSetDevice(h->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
   hipStream_t stream = (hipStream_t)o.stream;
   if (h->scratch_device >= 0 && h->scratch_device != h->device) return fail(MPS_EINVAL, "handle moved device");
-  if (total > h->scratch_bytes) {
-    if (h->scratch) {
-      if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-      (void)hipFree(h->scratch);
-      h->scratch = nullptr;
-      h->scratch_bytes = 0;
+
+  // ---- where each site tensor lives; which sites are staged ----
+  // A site is used in place when it is device-resident complex64.  A site in
+  // another stored form is expanded on the device into one of two slots (by
+  // site parity); a host-resident site is first copied, on the side stream,
+  // into one of two copy slots, one site ahead of the computation.
+  std::vector<char> host_site(single ? Mmax : 0, 0), staged(single ? Mmax : 0, 0);
+  size_t dec_max = 0, comp_max = 0;
+  bool any_staged = false;
+  for (int b = 0; b < B; ++b) {
+    const Chain& c = chains[b];
+    for (int k = 0; k < c.M; ++k) {
+      hipPointerAttribute_t attr;
+      std::memset(&attr, 0, sizeof attr);
+      e = hipPointerGetAttributes(&attr, c.tensors[k]);
+      if (e != hipSuccess) (void)hipGetLastError();
+      const bool on_dev = e == hipSuccess && attr.type == hipMemoryTypeDevice;
+      const bool on_host = e == hipSuccess && attr.type == hipMemoryTypeHost;
+      if (!on_dev && !on_host)
+        return fail(MPS_EINVAL, "chain %d site %d: tensor is neither device memory nor pinned host memory", b, k);
+      if (!single) {
+        if (!on_dev) return fail(MPS_EINVAL, "chain %d site %d: batched site tensors must be device-resident", b, k);
+        continue;
+      }
+      host_site[k] = on_host;
+      staged[k] = on_host || kind != MPS_C64;
+      any_staged = any_staged || staged[k];
+      if (staged[k]) dec_max = std::max(dec_max, (size_t)c.chi[k] * c.d[k] * c.chi[k + 1] * sizeof(float2));
+      if (on_host) comp_max = std::max(comp_max, mps::stored_bytes(kind, c.chi[k], c.d[k], c.chi[k + 1]));
     }
-    if ((e = hipMalloc(&h->scratch, total)) != hipSuccess) {
-      h->scratch = nullptr;
-      (void)hipGetLastError();
-      return fail(MPS_ENOMEM, "hipMalloc(%zu) failed: %s", total, hipGetErrorString(e));
-    }
-    h->scratch_bytes = total;
-    h->scratch_device = h->device;
   }
+  const bool any_host = comp_max > 0;
+  const size_t stage_need = any_staged ? 2 * align_up(dec_max) + 2 * align_up(comp_max) : 0;
+
+  // Order of the sweep.  Without staged sites the chunks are the outer loop
+  // and each chunk walks every site with one reused left-vector state.  With
+  // staged sites the sites are the outer loop, so that every site tensor is
+  // copied and expanded once per call: each chunk then keeps its own state,
+  // and the chunks take turns at every site (Section 3.1: a site's tensor is
+  // read once and applied to all samples of the macro batch).
+  const bool site_outer = any_staged;
+
+  // ---- plan the chunk ----
+  int64_t nc = o.n_chunk > 0 ? o.n_chunk : kDefaultChunk;
+  nc = std::min<int64_t>(nc, N);
+  nc = std::min<int64_t>(nc, (int64_t)1 << 30);
+  auto nstate_for = [&](int64_t rows) -> int64_t { return site_outer ? (N + rows - 1) / rows : 1; };
+  // problem tables: one set per left-vector state, plus the chunk arguments
+  auto table_for = [&](int64_t nstate) -> size_t {
+    size_t t = 0;
+    for (const Chain& c : chains)
+      t += (size_t)c.M * (sizeof(mps::ContractProb) + sizeof(mps::ContractLpProb) + sizeof(mps::PackProb) +
+                          sizeof(mps::MeasureProb) + 2 * sizeof(int));
+    t += (size_t)B * sizeof(mps::InitProb) + (size_t)Mmax * 7 * 256 + 4096;
+    return t * (size_t)nstate + (size_t)nstate * sizeof(mps::ChunkArgs) + 512;
+  };
+  auto scratch_for = [&](int64_t rows, std::vector<ChainBufs>* bufs) -> size_t {
+    const int64_t ns = nstate_for(rows);
+    size_t off = align_up(table_for(ns)) + align_up(sizeof(int));
+    for (int b = 0; b < B; ++b) {
+      ChainBufs cb;
+      off += chain_layout(rows, chains[b].sh, o.precision, ns, off, cb);
+      if (bufs) (*bufs)[b] = cb;
+    }
+    return off;
+  };
+  if (o.max_device_bytes > 0) {
+    // with one state per chunk, tiny chunks only multiply the tables
+    const int64_t floor_rows = site_outer ? std::min<int64_t>(N, 1024) : 1;
+    while (nc > floor_rows && (int64_t)(scratch_for(nc, nullptr) + stage_need) > o.max_device_bytes)
+      nc = std::max<int64_t>(floor_rows, (nc + 1) / 2);
+    if ((int64_t)(scratch_for(nc, nullptr) + stage_need) > o.max_device_bytes)
+      return fail(MPS_ENOMEM, "scratch for %lld-sample chunks (%zu B) plus site staging (%zu B) exceeds "
+                  "max_device_bytes (%lld)", (long long)nc, scratch_for(nc, nullptr), stage_need,
+                  (long long)o.max_device_bytes);
+  }
+  std::vector<ChainBufs> bufs(B);
+  const size_t total = scratch_for(nc, &bufs);
+  const int64_t nchunks = (N + nc - 1) / nc;
+  const int64_t nstate = nstate_for(nc);
+  const size_t table_bytes = table_for(nstate);
+
+  // ---- allocations (kept by the handle, grown on demand) ----
+  auto grow = [&](void*& ptr, size_t& have, size_t need, const char* what) -> int {
+    if (need <= have) return MPS_OK;
+    if (ptr) {
+      if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+      (void)hipFree(ptr);
+      ptr = nullptr;
+      have = 0;
+    }
+    if ((e = hipMalloc(&ptr, need)) != hipSuccess) {
+      ptr = nullptr;
+      (void)hipGetLastError();
+      return fail(MPS_ENOMEM, "hipMalloc(%zu) for %s failed: %s", need, what, hipGetErrorString(e));
+    }
+    have = need;
+    return MPS_OK;
+  };
+  int rc = grow(h->scratch, h->scratch_bytes, total, "sweep scratch");
+  if (rc) return rc;
+  h->scratch_device = h->device;
+  if ((rc = grow(h->stage, h->stage_bytes, stage_need, "site staging"))) return rc;
+  float2* dec_slot[2] = {nullptr, nullptr};
+  void* comp_slot[2] = {nullptr, nullptr};
+  if (any_staged) {
+    dec_slot[0] = (float2*)h->stage;
+    dec_slot[1] = (float2*)((char*)h->stage + align_up(dec_max));
+    comp_slot[0] = (char*)h->stage + 2 * align_up(dec_max);
+    comp_slot[1] = (char*)h->stage + 2 * align_up(dec_max) + align_up(comp_max);
+  }
+  if (any_host && !h->side) {
+    if ((e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking)) != hipSuccess)
+      return hip_fail(e, "hipStreamCreateWithFlags");
+  }
+  for (int i = 0; i < 2 && any_staged; ++i) {
+    if (!h->ev_copy[i] && (e = hipEventCreateWithFlags(&h->ev_copy[i], hipEventDisableTiming)) != hipSuccess)
+      return hip_fail(e, "hipEventCreate");
+    if (!h->ev_expand[i] && (e = hipEventCreateWithFlags(&h->ev_expand[i], hipEventDisableTiming)) != hipSuccess)
+      return hip_fail(e, "hipEventCreate");
+  }
+  auto site_A = [&](int b, int k) -> const float2* {
+    return (single && staged[k]) ? dec_slot[k & 1] : (const float2*)chains[b].tensors[k];
+  };
+
   char* const base = (char*)h->scratch;
   char* const dtab = base;                                  // problem tables
   int* const nflag = (int*)(base + align_up(table_bytes));  // flagged-sample counter
-  char* const cbase = base + fixed;                         // per-chain buffers
-  auto at = [&](size_t off) -> void* { return cbase + off; };
+  auto at = [&](size_t off) -> void* { return base + off; };
 
-  // ---- problem tables ----
+  // ---- problem tables, one set per left-vector state ----
   Tables tab;
-  std::vector<mps::InitProb> init(B);
-  for (int b = 0; b < B; ++b) {
-    mps::InitProb& ip = init[b];
-    ip.L = lowp ? at(bufs[b].Lh) : at(bufs[b].L);
-    ip.Ll = (o.precision == MPS_BF16X3) ? at(bufs[b].Ll) : nullptr;
-    ip.ld = mps::lp_pad_k(1);
-    ip.logp_in_call = chains[b].logp != nullptr;
-    ip.logp = chains[b].logp ? chains[b].logp : (double*)at(bufs[b].logp);
-  }
-  const size_t init_off = tab.put(init);
-  std::vector<Step> steps(Mmax);
-  for (int k = 0; k < Mmax; ++k) {
-    std::vector<mps::ContractProb> cf;
-    std::vector<mps::ContractLpProb> cl;
-    std::vector<mps::PackProb> pk;
-    std::vector<mps::MeasureProb> ms;
-    std::vector<int> tns(1, 0), blks(1, 0);
-    Step& sp = steps[k];
+  std::vector<size_t> init_off(nstate);
+  std::vector<Step> steps((size_t)nstate * Mmax);
+  for (int64_t s = 0; s < nstate; ++s) {
+    auto sat = [&](int b, size_t off) -> void* { return at(off + (size_t)s * bufs[b].state); };
+    std::vector<mps::InitProb> init(B);
     for (int b = 0; b < B; ++b) {
-      const Chain& c = chains[b];
-      if (k >= c.M) continue;
-      const int K = c.chi[k], dk = c.d[k], chr = c.chi[k + 1];
-      int T;
-      if (lowp) {
-        const int CP = mps::lp_pad_cols(chr), Kp = mps::lp_pad_k(K);
-        T = CP / mps::kLpBNC;
-        mps::PackProb pp{(const float2*)c.tensors[k], at(bufs[b].Bh),
-                         o.precision == MPS_BF16X3 ? at(bufs[b].Bl) : nullptr, K, dk, chr, CP, Kp};
-        pk.push_back(pp);
-        blks.push_back(blks.back() + (CP / 64) * (Kp / 64) * dk);
-        mps::ContractLpProb cp{at(bufs[b].Lh), o.precision == MPS_BF16X3 ? at(bufs[b].Ll) : nullptr, pp.Bh, pp.Bl,
-                               (float2*)at(bufs[b].W), (float*)at(bufs[b].qpart), Kp, dk, chr, CP};
-        cl.push_back(cp);
-      } else {
-        T = mps::col_tiles(chr);
-        mps::ContractProb cp{(const float2*)at(bufs[b].L), (const float2*)c.tensors[k], (float2*)at(bufs[b].W),
-                             (float*)at(bufs[b].qpart), K, dk, chr};
-        cf.push_back(cp);
-      }
-      tns.push_back(tns.back() + dk * T);
-      mps::MeasureProb mp{};
-      mp.W = (const float2*)at(bufs[b].W);
-      mp.qpart = (const float*)at(bufs[b].qpart);
-      mp.Lout = lowp ? nullptr : (float2*)at(bufs[b].L);
-      mp.Lh = lowp ? at(bufs[b].Lh) : nullptr;
-      mp.Ll = o.precision == MPS_BF16X3 ? at(bufs[b].Ll) : nullptr;
-      mp.ld_out = mps::lp_pad_k(chr);
-      mp.d = dk;
-      mp.chi_r = chr;
-      mp.T = T;
-      mp.site = k;
-      mp.M = c.M;
-      mp.mps_id = c.mps_id;
-      mp.outcomes = c.outcomes;
-      mp.logp_in_call = c.logp != nullptr;
-      mp.logp = c.logp ? c.logp : (double*)at(bufs[b].logp);
-      if (single && o.emit_n > 0) {
-        mp.emit_n = o.emit_n;
-        mp.emit_dmax = o.emit_dmax;
-        mp.emit_probs = o.emit_probs;
-        mp.emit_u = o.emit_u;
-      }
-      if (single) mp.mu = (const float2*)o.displace;
-      ms.push_back(mp);
-      sp.flops_per_row += 8.0 * (double)K * dk * chr;
-      // partial weights read + chosen branch read + new left vector write + outcome + logp read/write
-      sp.meas_bytes_per_row += (double)dk * T * 4 + 2.0 * chr * 8 + 4 + 16;
+      mps::InitProb& ip = init[b];
+      ip.L = lowp ? sat(b, bufs[b].Lh) : sat(b, bufs[b].L);
+      ip.Ll = split ? sat(b, bufs[b].Ll) : nullptr;
+      ip.ld = mps::lp_pad_k(1);
+      ip.logp_in_call = chains[b].logp != nullptr;
+      ip.logp = chains[b].logp ? chains[b].logp : (double*)sat(b, bufs[b].logp);
     }
-    sp.nprob = (int)ms.size();
-    sp.tn_total = tns.back();
-    sp.blk_total = blks.back();
-    sp.contract = lowp ? tab.put(cl) : tab.put(cf);
-    sp.tn_start = tab.put(tns);
-    sp.pack = tab.put(pk);
-    sp.blk_start = tab.put(blks);
-    sp.measure = tab.put(ms);
+    init_off[s] = tab.put(init);
+    for (int k = 0; k < Mmax; ++k) {
+      std::vector<mps::ContractProb> cf;
+      std::vector<mps::ContractLpProb> cl;
+      std::vector<mps::PackProb> pk;
+      std::vector<mps::MeasureProb> ms;
+      std::vector<int> tns(1, 0), blks(1, 0);
+      Step& sp = steps[(size_t)s * Mmax + k];
+      for (int b = 0; b < B; ++b) {
+        const Chain& c = chains[b];
+        if (k >= c.M) continue;
+        const int K = c.chi[k], dk = c.d[k], chr = c.chi[k + 1];
+        int T;
+        if (lowp) {
+          const int CP = mps::lp_pad_cols(chr), Kp = mps::lp_pad_k(K);
+          T = CP / mps::kLpBNC;
+          mps::PackProb pp{site_A(b, k), at(bufs[b].Bh), split ? at(bufs[b].Bl) : nullptr, K, dk, chr, CP, Kp};
+          pk.push_back(pp);
+          blks.push_back(blks.back() + (CP / 64) * (Kp / 64) * dk);
+          mps::ContractLpProb cp{sat(b, bufs[b].Lh), split ? sat(b, bufs[b].Ll) : nullptr, pp.Bh, pp.Bl,
+                                 (float2*)at(bufs[b].W), (float*)at(bufs[b].qpart), Kp, dk, chr, CP};
+          cl.push_back(cp);
+        } else {
+          T = mps::col_tiles(chr);
+          mps::ContractProb cp{(const float2*)sat(b, bufs[b].L), site_A(b, k), (float2*)at(bufs[b].W),
+                               (float*)at(bufs[b].qpart), K, dk, chr};
+          cf.push_back(cp);
+        }
+        tns.push_back(tns.back() + dk * T);
+        mps::MeasureProb mp{};
+        mp.W = (const float2*)at(bufs[b].W);
+        mp.qpart = (const float*)at(bufs[b].qpart);
+        mp.Lout = lowp ? nullptr : (float2*)sat(b, bufs[b].L);
+        mp.Lh = lowp ? sat(b, bufs[b].Lh) : nullptr;
+        mp.Ll = split ? sat(b, bufs[b].Ll) : nullptr;
+        mp.ld_out = mps::lp_pad_k(chr);
+        mp.d = dk;
+        mp.chi_r = chr;
+        mp.T = T;
+        mp.site = k;
+        mp.M = c.M;
+        mp.mps_id = c.mps_id;
+        mp.outcomes = c.outcomes;
+        mp.logp_in_call = c.logp != nullptr;
+        mp.logp = c.logp ? c.logp : (double*)sat(b, bufs[b].logp);
+        if (single && o.emit_n > 0) {
+          mp.emit_n = o.emit_n;
+          mp.emit_dmax = o.emit_dmax;
+          mp.emit_probs = o.emit_probs;
+          mp.emit_u = o.emit_u;
+        }
+        if (single) mp.mu = (const float2*)o.displace;
+        ms.push_back(mp);
+        sp.flops_per_row += 8.0 * (double)K * dk * chr;
+        // partial weights read + chosen branch read + new left vector write + outcome + logp read/write
+        sp.meas_bytes_per_row += (double)dk * T * 4 + 2.0 * chr * 8 + 4 + 16;
+      }
+      sp.nprob = (int)ms.size();
+      sp.tn_total = tns.back();
+      sp.blk_total = blks.back();
+      sp.contract = lowp ? tab.put(cl) : tab.put(cf);
+      sp.tn_start = tab.put(tns);
+      sp.pack = tab.put(pk);
+      sp.blk_start = tab.put(blks);
+      sp.measure = tab.put(ms);
+    }
   }
-  // ---- launches ----
-  // The current chunk's (rows, c0, n_offset) live in a device slot that every
-  // kernel reads; it is refreshed by a stream-ordered copy before each chunk.
-  const size_t cur_off = tab.put(std::vector<mps::ChunkArgs>(1));
+  // Chunk arguments.  Chunks-outer: one "current chunk" slot that every kernel
+  // reads, refreshed by a stream-ordered copy before each chunk (so that one
+  // captured graph serves every chunk).  Sites-outer: one entry per chunk.
+  std::vector<mps::ChunkArgs> cargs(nchunks);  // host copies; live until the final synchronisation
+  for (int64_t c = 0; c < nchunks; ++c)
+    cargs[c] = mps::ChunkArgs{(int)std::min<int64_t>(nc, N - c * nc), 0, c * nc, n_offset};
+  const size_t chunk_off = site_outer ? tab.put(cargs) : tab.put(std::vector<mps::ChunkArgs>(1));
   if (tab.blob.size() > table_bytes) return fail(MPS_EINVAL, "internal: problem tables exceed their reservation");
   if ((e = hipMemcpyAsync(dtab, tab.blob.data(), tab.blob.size(), hipMemcpyHostToDevice, stream)) != hipSuccess)
     return hip_fail(e, "hipMemcpyAsync (problem tables)");
-  const mps::ChunkArgs* cur = (const mps::ChunkArgs*)(dtab + cur_off);
-  const int64_t nchunks = (N + nc - 1) / nc;
-  std::vector<mps::ChunkArgs> cargs(nchunks);  // host copies; live until the final synchronisation
-  for (int64_t c = 0; c < nchunks; ++c) cargs[c] = mps::ChunkArgs{(int)std::min<int64_t>(nc, N - c * nc), 0, c * nc, n_offset};
+  const mps::ChunkArgs* const chunk_tab = (const mps::ChunkArgs*)(dtab + chunk_off);
 
+  // ---- launches ----
   const int group = o.tile_group > 0 ? o.tile_group : kDefaultGroup;
   const bool prof = o.profile != 0;
-  const bool use_graph = o.graph != 0 && stream != nullptr && !prof && nchunks > 1;
-  const size_t nev = prof ? (size_t)6 * Mmax : 0;
+  const bool use_graph = o.graph != 0 && stream != nullptr && !prof && nchunks > 1 && !site_outer;
+  // Timing events per site: pack, contraction, measurement, copy, expansion
+  // (begin, end); a pair is summed once its end has been recorded and waited.
+  constexpr int EV = 10;
+  const size_t nev = prof ? (size_t)EV * Mmax : 0;
   while (h->events.size() < nev) {
     hipEvent_t ev;
     if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_fail(e, "hipEventCreate");
     h->events.push_back(ev);
   }
-  auto mark = [&](int k, int which) -> hipError_t {
-    return prof ? hipEventRecord(h->events[6 * k + which], stream) : hipSuccess;
+  std::vector<unsigned> rec(prof ? Mmax : 0, 0u);
+  auto mark = [&](int k, int which, hipStream_t s) -> int {
+    if (!prof) return MPS_OK;
+    if (which & 1) rec[k] |= 1u << (which >> 1);
+    hipError_t e2 = hipEventRecord(h->events[EV * k + which], s);
+    return e2 == hipSuccess ? MPS_OK : hip_fail(e2, "hipEventRecord");
   };
   auto tp = [&](size_t off) { return (const void*)(dtab + off); };
 
-  // All launches of one chunk, grids sized for grid_rows rows.
+#define MPS_TRY(x)            \
+  do {                        \
+    const int rc_ = (x);      \
+    if (rc_) return rc_;      \
+  } while (0)
+#define MPS_HIP(x, what)                              \
+  do {                                                \
+    const hipError_t e_ = (x);                        \
+    if (e_ != hipSuccess) return hip_fail(e_, what);  \
+  } while (0)
+
+  auto run_init = [&](int64_t s, const mps::ChunkArgs* ch, int grid_rows) -> int {
+    MPS_HIP(mps::launch_init(form, (const mps::InitProb*)tp(init_off[s]), B, ch, grid_rows, stream), "init kernel");
+    return MPS_OK;
+  };
+  auto run_pack = [&](int k) -> int {
+    if (!lowp) return MPS_OK;
+    const Step& sp = steps[k];
+    MPS_TRY(mark(k, 0, stream));
+    MPS_HIP(mps::launch_pack_lp(form, (const mps::PackProb*)tp(sp.pack), (const int*)tp(sp.blk_start), sp.nprob,
+                                sp.blk_total, stream),
+            "pack launch");
+    return mark(k, 1, stream);
+  };
+  auto run_site = [&](int64_t s, int k, const mps::ChunkArgs* ch, int grid_rows) -> int {
+    const Step& sp = steps[(size_t)s * Mmax + k];
+    MPS_TRY(mark(k, 2, stream));
+    if (lowp)
+      e = mps::launch_contract_lp(form, (const mps::ContractLpProb*)tp(sp.contract), (const int*)tp(sp.tn_start),
+                                  sp.nprob, sp.tn_total, ch, grid_rows, group, stream);
+    else
+      e = mps::launch_contract_f32((const mps::ContractProb*)tp(sp.contract), (const int*)tp(sp.tn_start), sp.nprob,
+                                   sp.tn_total, ch, grid_rows, group, stream);
+    if (e != hipSuccess) return hip_fail(e, "contraction launch");
+    MPS_TRY(mark(k, 3, stream));
+    MPS_TRY(mark(k, 4, stream));
+    MPS_HIP(mps::launch_measure(form, (const mps::MeasureProb*)tp(sp.measure), sp.nprob, ch, grid_rows, seed, nflag,
+                                stream),
+            "measurement launch");
+    return mark(k, 5, stream);
+  };
+  // Host-resident site k: copy its stored bytes into copy slot k%2 on the
+  // side stream, once the expansion of site k-2 has finished reading the slot.
+  auto stage_copy = [&](int k) -> int {
+    const Chain& c = chains[0];
+    MPS_HIP(hipStreamWaitEvent(h->side, h->ev_expand[k & 1], 0), "hipStreamWaitEvent");
+    MPS_TRY(mark(k, 6, h->side));
+    MPS_HIP(hipMemcpyAsync(comp_slot[k & 1], c.tensors[k], mps::stored_bytes(kind, c.chi[k], c.d[k], c.chi[k + 1]),
+                           hipMemcpyHostToDevice, h->side),
+            "hipMemcpyAsync (site tensor)");
+    MPS_TRY(mark(k, 7, h->side));
+    MPS_HIP(hipEventRecord(h->ev_copy[k & 1], h->side), "hipEventRecord");
+    return MPS_OK;
+  };
+  // Staged site k: expand (after its copy) into slot k%2 on the compute stream.
+  auto stage_expand = [&](int k) -> int {
+    const Chain& c = chains[0];
+    const void* src = c.tensors[k];
+    if (host_site[k]) {
+      MPS_HIP(hipStreamWaitEvent(stream, h->ev_copy[k & 1], 0), "hipStreamWaitEvent");
+      src = comp_slot[k & 1];
+    }
+    MPS_TRY(mark(k, 8, stream));
+    mps::DecompressProb dp{src, dec_slot[k & 1], c.chi[k], c.d[k], c.chi[k + 1], kind};
+    MPS_HIP(mps::launch_decompress(dp, stream), "expand launch");
+    MPS_TRY(mark(k, 9, stream));
+    MPS_HIP(hipEventRecord(h->ev_expand[k & 1], stream), "hipEventRecord");
+    return MPS_OK;
+  };
+  // All launches of one chunk (chunks-outer order), grids sized for grid_rows.
   auto launch_chunk = [&](int grid_rows) -> int {
-    hipError_t e2;
-    if ((e2 = mps::launch_init(form, (const mps::InitProb*)tp(init_off), B, cur, grid_rows, stream)) != hipSuccess)
-      return hip_fail(e2, "init kernel");
+    const mps::ChunkArgs* cur = chunk_tab;
+    MPS_TRY(run_init(0, cur, grid_rows));
     for (int k = 0; k < Mmax; ++k) {
-      const Step& sp = steps[k];
-      if (lowp) {
-        if ((e2 = mark(k, 0)) != hipSuccess) return hip_fail(e2, "hipEventRecord");
-        e2 = mps::launch_pack_lp(form, (const mps::PackProb*)tp(sp.pack), (const int*)tp(sp.blk_start), sp.nprob,
-                                 sp.blk_total, stream);
-        if (e2 != hipSuccess) return hip_fail(e2, "pack launch");
-        if ((e2 = mark(k, 1)) != hipSuccess) return hip_fail(e2, "hipEventRecord");
-      }
-      if ((e2 = mark(k, 2)) != hipSuccess) return hip_fail(e2, "hipEventRecord");
-      if (lowp)
-        e2 = mps::launch_contract_lp(form, (const mps::ContractLpProb*)tp(sp.contract), (const int*)tp(sp.tn_start),
-                                     sp.nprob, sp.tn_total, cur, grid_rows, group, stream);
-      else
-        e2 = mps::launch_contract_f32((const mps::ContractProb*)tp(sp.contract), (const int*)tp(sp.tn_start),
-                                      sp.nprob, sp.tn_total, cur, grid_rows, group, stream);
-      if (e2 != hipSuccess) return hip_fail(e2, "contraction launch");
-      if ((e2 = mark(k, 3)) != hipSuccess) return hip_fail(e2, "hipEventRecord");
-      if ((e2 = mark(k, 4)) != hipSuccess) return hip_fail(e2, "hipEventRecord");
-      e2 = mps::launch_measure(form, (const mps::MeasureProb*)tp(sp.measure), sp.nprob, cur, grid_rows, seed, nflag,
-                               stream);
-      if (e2 != hipSuccess) return hip_fail(e2, "measurement launch");
-      if ((e2 = mark(k, 5)) != hipSuccess) return hip_fail(e2, "hipEventRecord");
+      MPS_TRY(run_pack(k));
+      MPS_TRY(run_site(0, k, cur, grid_rows));
     }
     return MPS_OK;
   };
 
   mps_stats st{};
   st.n_chunk = nc;
-  st.scratch_bytes = (int64_t)h->scratch_bytes;
+  st.scratch_bytes = (int64_t)(h->scratch_bytes + h->stage_bytes);
+  auto count = [&](int k, int rows, bool pack) {
+    const Step& sp = steps[k];
+    st.pack_launches += (lowp && pack) ? 1 : 0;
+    st.contract_launches++;
+    st.measure_launches++;
+    st.contract_flops += sp.flops_per_row * rows;
+    st.measure_bytes += sp.meas_bytes_per_row * rows;
+  };
+  // Wait for everything recorded so far and add up the timed pairs.
+  auto accumulate = [&]() -> int {
+    if (!prof) return MPS_OK;
+    MPS_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    if (h->side) MPS_HIP(hipStreamSynchronize(h->side), "hipStreamSynchronize");
+    double* dst[5] = {&st.pack_ms, &st.contract_ms, &st.measure_ms, &st.h2d_ms, &st.expand_ms};
+    for (int k = 0; k < Mmax; ++k) {
+      for (int p = 0; p < 5; ++p) {
+        if (!(rec[k] & (1u << p))) continue;
+        float ms = 0.f;
+        MPS_HIP(hipEventElapsedTime(&ms, h->events[EV * k + 2 * p], h->events[EV * k + 2 * p + 1]),
+                "hipEventElapsedTime");
+        *dst[p] += ms;
+      }
+      rec[k] = 0;
+    }
+    return MPS_OK;
+  };
+#undef MPS_TRY
+#undef MPS_HIP
+
   if ((e = mps::launch_zero_int(nflag, 1, stream)) != hipSuccess) return hip_fail(e, "zero kernel");
 
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  if (use_graph) {
-    // Chunks shorter than nc (the tail) replay the same graph: every kernel
-    // masks rows >= the slot's row count.
-    if ((e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-      return hip_fail(e, "hipStreamBeginCapture");
-    const int rc = launch_chunk((int)nc);
-    hipError_t ee = hipStreamEndCapture(stream, &graph);
-    if (rc != MPS_OK) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return rc;
-    }
-    if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
-    if ((e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0)) != hipSuccess) {
-      (void)hipGraphDestroy(graph);
-      return hip_fail(e, "hipGraphInstantiate");
-    }
-  }
-  int rc = MPS_OK;
-  for (int64_t c = 0; c < nchunks && rc == MPS_OK; ++c) {
-    const mps::ChunkArgs& ch = cargs[c];
-    if ((e = hipMemcpyAsync((void*)cur, &ch, sizeof ch, hipMemcpyHostToDevice, stream)) != hipSuccess) {
-      rc = hip_fail(e, "hipMemcpyAsync (chunk arguments)");
-      break;
-    }
-    if (use_graph) {
-      if ((e = hipGraphLaunch(gexec, stream)) != hipSuccess) rc = hip_fail(e, "hipGraphLaunch");
-    } else {
-      rc = launch_chunk(ch.rows);
-    }
-    if (rc != MPS_OK) break;
-    for (int k = 0; k < Mmax; ++k) {
-      st.pack_launches += lowp ? 1 : 0;
-      st.contract_launches++;
-      st.measure_launches++;
-      st.contract_flops += steps[k].flops_per_row * ch.rows;
-      st.measure_bytes += steps[k].meas_bytes_per_row * ch.rows;
-    }
-    if (prof) {
-      if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-      for (int k = 0; k < Mmax; ++k) {
-        float a = 0.f, b = 0.f, c2 = 0.f;
-        if (lowp && (e = hipEventElapsedTime(&c2, h->events[6 * k], h->events[6 * k + 1])) != hipSuccess)
-          return hip_fail(e, "hipEventElapsedTime");
-        if ((e = hipEventElapsedTime(&a, h->events[6 * k + 2], h->events[6 * k + 3])) != hipSuccess)
-          return hip_fail(e, "hipEventElapsedTime");
-        if ((e = hipEventElapsedTime(&b, h->events[6 * k + 4], h->events[6 * k + 5])) != hipSuccess)
-          return hip_fail(e, "hipEventElapsedTime");
-        st.contract_ms += a;
-        st.measure_ms += b;
-        st.pack_ms += c2;
+  if (site_outer) {
+    for (int64_t c = 0; c < nchunks && rc == MPS_OK; ++c) rc = run_init(c, chunk_tab + c, cargs[c].rows);
+    if (rc == MPS_OK && host_site[0]) rc = stage_copy(0);
+    for (int k = 0; k < Mmax && rc == MPS_OK; ++k) {
+      if (k + 1 < Mmax && host_site[k + 1] && (rc = stage_copy(k + 1))) break;
+      if (staged[k] && (rc = stage_expand(k))) break;
+      if (staged[k]) {
+        const Chain& c = chains[0];
+        st.staged_sites++;
+        if (host_site[k]) st.h2d_bytes += (double)mps::stored_bytes(kind, c.chi[k], c.d[k], c.chi[k + 1]);
+      }
+      if ((rc = run_pack(k))) break;
+      for (int64_t c = 0; c < nchunks && rc == MPS_OK; ++c) {
+        rc = run_site(c, k, chunk_tab + c, cargs[c].rows);
+        if (rc == MPS_OK) {
+          count(k, cargs[c].rows, c == 0);
+          rc = accumulate();
+        }
       }
     }
+  } else {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    if (use_graph) {
+      // Chunks shorter than nc (the tail) replay the same graph: every kernel
+      // masks rows >= the slot's row count.
+      if ((e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return hip_fail(e, "hipStreamBeginCapture");
+      rc = launch_chunk((int)nc);
+      hipError_t ee = hipStreamEndCapture(stream, &graph);
+      if (rc != MPS_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+      }
+      if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
+      if ((e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0)) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e, "hipGraphInstantiate");
+      }
+    }
+    for (int64_t c = 0; c < nchunks && rc == MPS_OK; ++c) {
+      const mps::ChunkArgs& ch = cargs[c];
+      if ((e = hipMemcpyAsync((void*)chunk_tab, &ch, sizeof ch, hipMemcpyHostToDevice, stream)) != hipSuccess) {
+        rc = hip_fail(e, "hipMemcpyAsync (chunk arguments)");
+        break;
+      }
+      if (use_graph) {
+        if ((e = hipGraphLaunch(gexec, stream)) != hipSuccess) rc = hip_fail(e, "hipGraphLaunch");
+      } else {
+        rc = launch_chunk(ch.rows);
+      }
+      if (rc != MPS_OK) break;
+      for (int k = 0; k < Mmax; ++k) count(k, ch.rows, true);
+      rc = accumulate();
+    }
+    if (use_graph) {
+      (void)hipStreamSynchronize(stream);
+      (void)hipGraphExecDestroy(gexec);
+      (void)hipGraphDestroy(graph);
+    }
   }
-  if (use_graph) {
-    (void)hipStreamSynchronize(stream);
-    (void)hipGraphExecDestroy(gexec);
-    (void)hipGraphDestroy(graph);
+  if (rc != MPS_OK) {
+    // no copy may still read the caller's host buffers after the return
+    if (h->side) (void)hipStreamSynchronize(h->side);
+    return rc;
   }
-  if (rc != MPS_OK) return rc;
 
   int flagged = 0;
   if ((e = hipMemcpyAsync(&flagged, nflag, sizeof(int), hipMemcpyDeviceToHost, stream)) != hipSuccess)
@@ -471,7 +681,7 @@ int check_call(mps_handle h, int32_t dtype, int64_t N, int64_t n_offset) {
   if (N < 0) return fail(MPS_EINVAL, "N = %lld < 0", (long long)N);
   if (n_offset < 0) return fail(MPS_EINVAL, "n_offset < 0");
   if (N > INT64_MAX - n_offset) return fail(MPS_EINVAL, "n_offset + N overflows");
-  if (dtype != MPS_C64) return fail(MPS_EINVAL, "unknown dtype %d", dtype);
+  if (dtype != MPS_C64 && dtype != MPS_CF16 && dtype != MPS_CF8) return fail(MPS_EINVAL, "unknown dtype %d", dtype);
   return MPS_OK;
 }
 
@@ -526,8 +736,15 @@ void mps_destroy(mps_handle h) {
     int prev = 0;
     if (hipGetDevice(&prev) == hipSuccess) {
       if (hipSetDevice(h->scratch_device) == hipSuccess) {
+        if (h->side) (void)hipStreamSynchronize(h->side);
         for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+        for (int i = 0; i < 2; ++i) {
+          if (h->ev_copy[i]) (void)hipEventDestroy(h->ev_copy[i]);
+          if (h->ev_expand[i]) (void)hipEventDestroy(h->ev_expand[i]);
+        }
+        if (h->side) (void)hipStreamDestroy(h->side);
         if (h->scratch) (void)hipFree(h->scratch);
+        if (h->stage) (void)hipFree(h->stage);
         (void)hipSetDevice(prev);
       }
     }
@@ -549,7 +766,7 @@ int mps_sample(mps_handle h, const void* const* tensors, int32_t dtype, const in
     return MPS_OK;
   }
   if (!outcomes) return fail(MPS_EINVAL, "outcomes is NULL");
-  return run_sweep(h, chains, N, n_offset, seed, true);
+  return run_sweep(h, chains, N, n_offset, seed, true, dtype);
 }
 
 int mps_sample_batch(mps_handle h, int32_t B, const mps_chain* chains_in, int32_t dtype, int64_t N,
@@ -557,6 +774,7 @@ int mps_sample_batch(mps_handle h, int32_t B, const mps_chain* chains_in, int32_
   int rc = check_call(h, dtype, N, n_offset);
   if (rc) return rc;
   if (B < 1 || B > kMaxChains) return fail(MPS_EINVAL, "B = %d out of [1, %d]", B, kMaxChains);
+  if (dtype != MPS_C64) return fail(MPS_EINVAL, "batched site tensors must be MPS_C64");
   if (!chains_in) return fail(MPS_EINVAL, "chains is NULL");
   std::vector<Chain> chains(B);
   for (int b = 0; b < B; ++b) {
@@ -570,7 +788,7 @@ int mps_sample_batch(mps_handle h, int32_t B, const mps_chain* chains_in, int32_
     h->st.scratch_bytes = (int64_t)h->scratch_bytes;
     return MPS_OK;
   }
-  return run_sweep(h, chains, N, n_offset, seed, false);
+  return run_sweep(h, chains, N, n_offset, seed, false, dtype);
 }
 
 }  // extern "C"

@@ -108,6 +108,16 @@ struct InitProb {
   int logp_in_call;
 };
 
+// Stored site tensor (device memory) -> complex64 site tensor.
+struct DecompressProb {
+  const void* src;
+  float2* dst;
+  int chi_l, d, chi_r;
+  int kind;  // 0 complex64, 1 complex-fp16, 2 complex-fp8 with 128x128 block scales
+};
+size_t stored_bytes(int kind, int chi_l, int d, int chi_r);
+hipError_t launch_decompress(const DecompressProb& p, hipStream_t s);
+
 hipError_t launch_zero_int(int* p, int n, hipStream_t s);
 // form: 0 = FP32 path, kBf16x3, kFp16
 hipError_t launch_init(int form, const InitProb* probs, int nprob, const ChunkArgs* ch, int grid_rows, hipStream_t s);

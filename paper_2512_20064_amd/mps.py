@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(HERE, "libmps.so")
 MPS_OK, MPS_EINVAL, MPS_ENOMEM, MPS_ENODEV, MPS_EHIP, MPS_ENUMERIC = 0, -1, -2, -3, -4, -5
 MPS_FP32, MPS_BF16X3, MPS_FP16 = 0, 1, 2
 PRECISIONS = {"fp32": MPS_FP32, "bf16x3": MPS_BF16X3, "fp16": MPS_FP16}
-MPS_C64 = 0
+MPS_C64, MPS_CF16, MPS_CF8 = 0, 1, 2
+STORAGE = {"c64": MPS_C64, "cf16": MPS_CF16, "cf8": MPS_CF8}
 
 STATUS_NAMES = {0: "MPS_OK", -1: "MPS_EINVAL", -2: "MPS_ENOMEM", -3: "MPS_ENODEV",
                 -4: "MPS_EHIP", -5: "MPS_ENUMERIC"}
@@ -72,6 +73,10 @@ class mps_stats(ctypes.Structure):
         ("n_chunk", ctypes.c_int64),
         ("flagged", ctypes.c_int64),
         ("scratch_bytes", ctypes.c_int64),
+        ("h2d_bytes", ctypes.c_double),
+        ("h2d_ms", ctypes.c_double),
+        ("expand_ms", ctypes.c_double),
+        ("staged_sites", ctypes.c_int64),
     ]
 
 
@@ -298,3 +303,46 @@ class Sampler:
             raise MPSError(rc, mps_last_error())
         self.stats = mps_get_stats(self.h)
         return outs
+
+    def sample_stored(self, stored, shapes, kind: str, N: int, seed: int, n_offset: int = 0, emit_n: int = 0,
+                      emit_dmax: int = 0, stream=None, raise_numeric: bool = False):
+        """Sample from site tensors held in a stored form.
+
+        stored: list of M uint8 torch tensors (CUDA, or pinned CPU memory), one
+        per site, holding the bytes of the site in storage `kind` ("c64",
+        "cf16" or "cf8"); shapes: the M (chi_l, d, chi_r) site shapes.
+        """
+        import torch
+        dev = torch.device("cuda", self.device)
+        M = len(stored)
+        chi = [int(shapes[0][0])] + [int(s[2]) for s in shapes]
+        d = [int(s[1]) for s in shapes]
+        for t in stored:
+            if t.dtype != torch.uint8 or not t.is_contiguous() or not (t.is_cuda or t.is_pinned()):
+                raise ValueError("stored sites must be contiguous uint8 tensors on the GPU or in pinned memory")
+        outcomes = torch.empty((N, M), dtype=torch.int32, device=dev)
+        logp = torch.empty((N,), dtype=torch.float64, device=dev)
+        emit_probs = emit_u = None
+        opt = mps_options.from_buffer_copy(self.opt)
+        if emit_n:
+            emit_dmax = emit_dmax or max(d)
+            emit_probs = torch.full((emit_n, M, emit_dmax), float("nan"), dtype=torch.float64, device=dev)
+            emit_u = torch.zeros((emit_n, M), dtype=torch.float64, device=dev)
+            opt.emit_n = emit_n
+            opt.emit_dmax = emit_dmax
+            opt.emit_probs = emit_probs.data_ptr()
+            opt.emit_u = emit_u.data_ptr()
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        opt.stream = s.cuda_stream
+        mps_set_options(self.h, opt)
+        rc = mps_sample(self.h, [t.data_ptr() for t in stored], STORAGE[kind], chi, d, M, N, n_offset, seed,
+                        outcomes.data_ptr(), logp.data_ptr())
+        self.status = rc
+        if rc and (rc != MPS_ENUMERIC or raise_numeric):
+            raise MPSError(rc, mps_last_error())
+        self.stats = mps_get_stats(self.h)
+        out = {"outcomes": outcomes, "logp": logp, "status": rc}
+        if emit_n:
+            out["probs"] = emit_probs
+            out["u"] = emit_u
+        return out

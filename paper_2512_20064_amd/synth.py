@@ -184,3 +184,100 @@ def promote(tensors: list[np.ndarray]) -> list[np.ndarray]:
             seen[id(t)] = t.astype(np.complex128)
         out.append(seen[id(t)])
     return out
+
+
+# --------------------------------------------------------------------------
+# Compressed storage of site tensors (Section 3.3.2: tensors stored and moved
+# in low precision).  These produce input bytes; both the sampler (which
+# decodes them on the GPU) and the oracle (which decodes them with its own
+# code) consume the same bytes.
+#
+#   complex-fp16: (re, im) as IEEE binary16, interleaved, 4 bytes per entry.
+#   complex-fp8 : (re, im) as OCP FP8 E4M3 codes, interleaved, 2 bytes per
+#                 entry, followed (at the next multiple of 256 bytes) by FP32
+#                 scales, one per 128 x 128 block of the chi_l x (d*chi_r)
+#                 complex matrix, row-major over blocks; an entry decodes to
+#                 code_value * scale of its block.  Scales map each block's
+#                 largest |re| or |im| to 448 (the largest E4M3 value).
+# --------------------------------------------------------------------------
+
+FP8_BLOCK = 128
+E4M3_MAX = 448.0
+
+
+def _e4m3_grid() -> np.ndarray:
+    """Values of the 256 E4M3 codes (OCP 8-bit floating point, E4M3): sign,
+    4 exponent bits with bias 7, 3 mantissa bits, subnormals, and the single
+    NaN pattern S.1111.111 (no infinities)."""
+    vals = np.empty(256)
+    for c in range(256):
+        s = -1.0 if c & 0x80 else 1.0
+        e = (c >> 3) & 0xF
+        m = c & 0x7
+        if e == 0xF and m == 0x7:
+            vals[c] = np.nan
+        elif e == 0:
+            vals[c] = s * (m / 8.0) * 2.0 ** -6
+        else:
+            vals[c] = s * (1.0 + m / 8.0) * 2.0 ** (e - 7)
+    return vals
+
+
+E4M3_VALUES = _e4m3_grid()
+
+
+def encode_e4m3(x: np.ndarray) -> np.ndarray:
+    """Round float values to the nearest E4M3 code (ties to an even mantissa),
+    saturating at +-448."""
+    x = np.clip(np.asarray(x, dtype=np.float64), -E4M3_MAX, E4M3_MAX)
+    pos = E4M3_VALUES[:0x7F]  # non-negative finite codes 0x00..0x7E, increasing
+    a = np.abs(x)
+    idx = np.searchsorted(pos, a)  # pos[idx-1] < a <= pos[idx]
+    idx = np.clip(idx, 1, len(pos) - 1)
+    lo, hi = pos[idx - 1], pos[idx]
+    pick_hi = (a - lo > hi - a) | ((a - lo == hi - a) & (idx % 2 == 0))
+    code = np.where(pick_hi, idx, idx - 1).astype(np.uint8)
+    code = np.where(a == 0, 0, code)
+    return np.where(x < 0, code | 0x80, code).astype(np.uint8)
+
+
+def compress_site(A: np.ndarray, kind: str) -> np.ndarray:
+    """Bytes of one site tensor (chi_l, d, chi_r) in the given storage kind."""
+    A = np.ascontiguousarray(A.astype(np.complex64))
+    if kind == "c64":
+        return A.view(np.uint8).reshape(-1).copy()
+    if kind == "cf16":
+        ri = np.stack([A.real, A.imag], axis=-1).astype(np.float16)
+        return ri.view(np.uint8).reshape(-1).copy()
+    if kind == "cf8":
+        chi_l, d, chi_r = A.shape
+        mat = A.reshape(chi_l, d * chi_r)
+        nbr, nbc = -(-chi_l // FP8_BLOCK), -(-(d * chi_r) // FP8_BLOCK)
+        scales = np.ones((nbr, nbc), dtype=np.float32)
+        codes = np.empty((chi_l, d * chi_r, 2), dtype=np.uint8)
+        for bi in range(nbr):
+            for bj in range(nbc):
+                blk = mat[bi * FP8_BLOCK:(bi + 1) * FP8_BLOCK, bj * FP8_BLOCK:(bj + 1) * FP8_BLOCK]
+                amax = float(max(np.abs(blk.real).max(), np.abs(blk.imag).max()))
+                sc = np.float32(amax / E4M3_MAX) if amax > 0 else np.float32(1.0)
+                scales[bi, bj] = sc
+                sl = (slice(bi * FP8_BLOCK, (bi + 1) * FP8_BLOCK), slice(bj * FP8_BLOCK, (bj + 1) * FP8_BLOCK))
+                codes[sl + (0,)] = encode_e4m3(blk.real / np.float64(sc))
+                codes[sl + (1,)] = encode_e4m3(blk.imag / np.float64(sc))
+        head = codes.reshape(-1)
+        off = -(-head.size // 256) * 256
+        out = np.zeros(off + scales.size * 4, dtype=np.uint8)
+        out[:head.size] = head
+        out[off:] = scales.view(np.uint8).reshape(-1)
+        return out
+    raise ValueError(kind)
+
+
+def compressed_bytes(chi_l: int, d: int, chi_r: int, kind: str) -> int:
+    n = chi_l * d * chi_r
+    if kind == "c64":
+        return 8 * n
+    if kind == "cf16":
+        return 4 * n
+    nb = -(-chi_l // FP8_BLOCK) * -(-(d * chi_r) // FP8_BLOCK)
+    return -(-2 * n // 256) * 256 + 4 * nb

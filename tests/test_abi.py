@@ -39,7 +39,7 @@ def test_exports_every_declared_symbol(lib):
 def test_options_struct_matches_header():
     # the binding's struct must have the header's size (8-byte aligned fields)
     assert ctypes.sizeof(mps.mps_options) == 4 + 4 + 8 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8 + 4 + 4 + 8
-    assert ctypes.sizeof(mps.mps_stats) == 11 * 8
+    assert ctypes.sizeof(mps.mps_stats) == 15 * 8
 
 
 def _call(h, **kw):
@@ -55,6 +55,7 @@ def _call(h, **kw):
     dict(N=-1),
     dict(n_offset=-5),
     dict(dtype=7),
+    dict(dtype=-1),
     dict(chi=[2, 4, 1]),                    # chi[0] != 1
     dict(chi=[1, 4, 0]),                    # bond < 1
     dict(chi=[1, 9, 1]),                    # chi[1] > d[1]*chi[2]: no right-canonical tensor

@@ -1,0 +1,138 @@
+"""Staged site tensors: pinned host memory and compressed storage
+(complex-fp16, complex-fp8 with 128 x 128 block scales), copied on a side
+stream and expanded on the device (Section 3.3.2; Section 3.1: every site is
+applied to all samples of the call before the next site)."""
+import numpy as np
+import pytest
+
+from oracle.sampler import _e4m3_value
+from paper_2512_20064_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _chain(M=10, d=3, chi=40, seed=31):
+    dl = [d] * M
+    return synth.to_c64(synth.random_mps(seed, dl, synth.ramp_bonds(dl, chi)))
+
+
+def _expand_f32(raw, shape, kind):
+    """complex64 values the device expansion produces: binary16 -> FP32 is
+    exact; an fp8 entry is its code's value times its block scale, one FP32
+    product."""
+    chi_l, d, chi_r = shape
+    n = chi_l * d * chi_r
+    if kind == "c64":
+        return raw[:8 * n].view(np.complex64).reshape(shape).copy()
+    if kind == "cf16":
+        ri = raw[:4 * n].view(np.float16).astype(np.float32).reshape(n, 2)
+        return (ri[:, 0] + 1j * ri[:, 1]).astype(np.complex64).reshape(shape)
+    codes = raw[:2 * n].reshape(chi_l, d * chi_r, 2)
+    off = -(-2 * n // 256) * 256
+    nbr, nbc = -(-chi_l // 128), -(-(d * chi_r) // 128)
+    sc = raw[off:off + 4 * nbr * nbc].view(np.float32).reshape(nbr, nbc)
+    sc = np.repeat(np.repeat(sc, 128, 0), 128, 1)[:chi_l, :d * chi_r]
+    re = _e4m3_value(codes[..., 0]).astype(np.float32) * sc
+    im = _e4m3_value(codes[..., 1]).astype(np.float32) * sc
+    out = np.empty((chi_l, d * chi_r), dtype=np.complex64)
+    out.real, out.imag = re, im
+    return out.reshape(shape)
+
+
+def _stored(tensors, kind, where):
+    """uint8 torch tensors per site: where is 'device', 'host' (pinned) or
+    'mixed' (even sites pinned host, odd sites device)."""
+    out = []
+    for k, A in enumerate(tensors):
+        raw = torch.from_numpy(synth.compress_site(A, kind))
+        on_host = where == "host" or (where == "mixed" and k % 2 == 0)
+        out.append(raw.pin_memory() if on_host else raw.to("cuda"))
+    return out
+
+
+CASES = [("c64", "host"), ("cf16", "device"), ("cf16", "host"), ("cf8", "device"), ("cf8", "mixed")]
+
+
+@pytest.mark.parametrize("form", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("kind,where", CASES)
+def test_staged_equals_resident_expanded_tensor(form, kind, where):
+    """A staged call is bit-identical to a device-resident complex64 call on
+    the expanded tensors (only where the bytes come from differs), across
+    4 chunks with a ragged tail."""
+    from paper_2512_20064_amd import mps
+    from tests.parity_util import upload
+    print(f"[gpu-case] staged {kind}/{where} vs resident {form}", flush=True)
+    ch = _chain()
+    shapes = [t.shape for t in ch]
+    raws = [synth.compress_site(t, kind) for t in ch]
+    expanded = [_expand_f32(r, s, kind) for r, s in zip(raws, shapes)]
+    N, seed = 1000, 606
+    s = mps.Sampler(0, n_chunk=256, precision=form)
+    ref = s.sample(upload(expanded), N, seed)
+    got = s.sample_stored(_stored(ch, kind, where), shapes, kind, N, seed)
+    torch.cuda.synchronize()
+    st = s.stats
+    s.close()
+    assert torch.equal(got["outcomes"], ref["outcomes"])
+    assert torch.equal(got["logp"], ref["logp"])
+    M = len(ch)
+    assert st.staged_sites == M
+    assert st.contract_launches == 4 * M
+    if form != "fp32":
+        assert st.pack_launches == M  # one packing per site, shared by the chunks
+    nb_host = sum(r.size for k, r in enumerate(raws) if where == "host" or (where == "mixed" and k % 2 == 0))
+    assert st.h2d_bytes == nb_host
+
+
+@pytest.mark.parametrize("kind", ["cf16", "cf8"])
+def test_staged_parity_with_oracle(kind):
+    """Compressed pinned-host sites against the FP64 oracle run on the same
+    (expanded) tensor values, forced-prefix protocol, FP32 bars."""
+    from paper_2512_20064_amd import mps
+    from tests.parity_util import compare
+    print(f"[gpu-case] staged {kind} host parity vs oracle", flush=True)
+    ch = _chain(M=14, d=4, chi=64, seed=7)
+    shapes = [t.shape for t in ch]
+    expanded = [_expand_f32(synth.compress_site(t, kind), t.shape, kind) for t in ch]
+    N, seed = 1536, 99
+    s = mps.Sampler(0, n_chunk=512)
+    r = s.sample_stored(_stored(ch, kind, "host"), shapes, kind, N, seed, emit_n=256)
+    torch.cuda.synchronize()
+    s.close()
+    gpu = {k: v.cpu().numpy() for k, v in r.items() if k != "status"}
+    rows = np.concatenate([np.arange(256), np.arange(N - 200, N)])
+    rep = compare(expanded, seed, gpu, rows=rows)
+    print(rep, flush=True)
+
+
+def test_staged_profile_times_copies_and_expansions():
+    from paper_2512_20064_amd import mps
+    print("[gpu-case] staged profile counters", flush=True)
+    ch = _chain(M=6, d=2, chi=256, seed=3)
+    shapes = [t.shape for t in ch]
+    s = mps.Sampler(0, n_chunk=128, profile=True, precision="bf16x3")
+    r = s.sample_stored(_stored(ch, "cf16", "host"), shapes, "cf16", 300, 5)
+    torch.cuda.synchronize()
+    st = s.stats
+    s.close()
+    assert r["status"] == 0
+    assert st.h2d_ms > 0 and st.expand_ms > 0 and st.contract_ms > 0 and st.pack_ms > 0
+    assert st.staged_sites == 6 and st.pack_launches == 6 and st.contract_launches == 18
+
+
+def test_pageable_host_sites_are_rejected():
+    from paper_2512_20064_amd import mps
+    print("[gpu-case] pageable host pointer rejected", flush=True)
+    ch = _chain(M=3, d=2, chi=4)
+    raws = [np.ascontiguousarray(synth.compress_site(t, "c64")) for t in ch]
+    chi = [1] + [t.shape[2] for t in ch]
+    d = [t.shape[1] for t in ch]
+    out = torch.empty((8, 3), dtype=torch.int32, device="cuda")
+    h = mps.mps_create(0)
+    try:
+        rc = mps.mps_sample(h, [r.ctypes.data for r in raws], mps.MPS_C64, chi, d, 3, 8, 0, 1, out.data_ptr(), 0)
+        assert rc == mps.MPS_EINVAL, (rc, mps.mps_last_error())
+        assert "pinned" in mps.mps_last_error()
+    finally:
+        mps.mps_destroy(h)
