@@ -9,8 +9,22 @@ GBS-shaped resident chain, M = 1024 sites, d = 4, chi = 1024 (bond ramp
 global samples [s*65536, (s+1)*65536) of the N = 2^20 job.
 
 Prints one JSON line: site-samples/s, the contraction kernel against the
-FP32 MFMA roofline (event-timed live over the timed region), and the FP64
-oracle timed on the host cores on a bounded sample of the same chain.
+MFMA roofline of its operand type (event-timed live over the timed region),
+and the FP64 oracle timed on the host cores on a bounded sample of the same
+chain.
+
+Other workloads (one JSON line each, not the headline):
+  --workload uneven   M = 2048, d_k in {2..6}, chi_k = min(prod d, 4096),
+                      structured right-canonical sites on the device
+                      (repeated shapes share a device buffer);
+  --workload batch    256 independent chains (M in [32, 512], chi in
+                      {16..256}, d in {2, 3, 4}), N = 8192 each: one batched
+                      call against one call per chain;
+  --workload stream   a 64-site window at chi = 10^4, d = 4, site tensors in
+                      pinned host memory compressed to complex-fp16 (or fp8
+                      with 128 x 128 block scales), copied on a side stream
+                      while the previous site computes: per-site time, H2D
+                      GB/s and the copy/compute overlap.
 """
 from __future__ import annotations
 
@@ -62,37 +76,52 @@ def log(msg):
 
 
 def build_chain(args):
+    """(t128 or None, device-ready complex64 tensors, d, chi, name)."""
     from paper_2512_20064_amd import synth
     t0 = time.time()
+    t128 = None
     if args.workload == "resident":
         t128, d, chi = synth.resident_chain(tensor_seed=3, M=args.sites, d=4, chi_max=args.chi, pool=args.pool)
         name = (f"resident chain M={args.sites} d=4 chi={args.chi} (ramp at both ends) complex64, "
                 f"{args.chunk} samples per step of an N=2^20 job")
+        t64 = synth.to_c64(t128)
     elif args.workload == "small":
         t128, d, chi = synth.small_chain(1, M=32, d=4, chi_max=32)
         name = "small chain M=32 d=4 chi=32 complex64"
+        t64 = synth.to_c64(t128)
+    elif args.workload == "uneven":
+        rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([4, 0, 0xD])))
+        d = [int(x) for x in rng.integers(2, 7, size=args.sites)]
+        t64, chi = synth.structured_chain(4, d, args.chi, pool=2, device="cuda")
+        name = (f"uneven chain M={args.sites} d_k~U{{2..6}} chi_k=min(prod d, {args.chi}) structured "
+                f"right-canonical complex64 (repeated shapes share a device buffer), "
+                f"{args.chunk} samples per step of an N=2^22 job")
     else:
         raise SystemExit(f"unknown workload {args.workload}")
-    t64 = synth.to_c64(t128)
     log(f"generated chain in {time.time() - t0:.1f}s")
     return t128, t64, d, chi, name
 
 
-def upload(t64):
-    """One device buffer per site; pooled host tensors are copied once and
-    cloned on the device."""
+def upload(t64, share=False):
+    """One device buffer per site (pooled host tensors are copied once and
+    cloned on the device), or, with share=True or device inputs, one buffer
+    per distinct tensor."""
     import torch
     cache = {}
     dev = []
     for t in t64:
         key = id(t)
         if key not in cache:
-            cache[key] = torch.from_numpy(t).to("cuda")
+            cache[key] = t if isinstance(t, torch.Tensor) else torch.from_numpy(t).to("cuda")
             dev.append(cache[key])
         else:
-            dev.append(cache[key].clone())
+            dev.append(cache[key] if (share or isinstance(t, torch.Tensor)) else cache[key].clone())
     torch.cuda.synchronize()
     return dev
+
+
+def distinct_bytes(dev):
+    return int(sum(t.numel() * t.element_size() for t in {id(t): t for t in dev}.values()))
 
 
 def cpu_baseline(t128, seed, n_samples, n_sites):
@@ -113,44 +142,39 @@ def cpu_baseline(t128, seed, n_samples, n_sites):
             "sample": f"{n_samples} samples x first {n_sites} sites of the same chain, numpy FP64, {dt:.1f}s"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="resident")
-    ap.add_argument("--sites", type=int, default=1024)
-    ap.add_argument("--chi", type=int, default=1024)
-    ap.add_argument("--pool", type=int, default=16)
-    ap.add_argument("--chunk", type=int, default=65536)
-    ap.add_argument("--precision", default="fp32", choices=sorted(FORMS))
-    ap.add_argument("--beside", default="", help="comma-separated forms also timed (e.g. fp32)")
-    ap.add_argument("--beside-steps", type=int, default=1)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-samples", type=int, default=1024)
-    ap.add_argument("--cpu-sites", type=int, default=512)
-    ap.add_argument("--no-profile", action="store_true", help="do not event-time each launch")
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="also run one plain device copy of this many MiB (reference for HBM counters)")
-    args = ap.parse_args()
+def roofline_of(form, c_fl, c_n, c_ms, dt, m_ms, p_ms, chunk):
+    f = FORMS[form]
+    alg = (c_fl / c_n) / (c_ms / c_n * 1e-3) / 1e12
+    achieved = alg * f["mfma_per_alg"]
+    return {
+        "bound": "mfma", "achieved": round(achieved, 2), "peak": f["peak"], "unit": "TFLOP/s",
+        "frac": round(achieved / f["peak"], 4), "traffic": traffic_for(form, chunk),
+        "kernel": f["kernel"], "algorithmic_tflops": round(alg, 2),
+        "mfma_products_per_complex_product": f["mfma_per_alg"],
+        "avg_launch_ms": round(c_ms / c_n, 4), "launches": c_n,
+        "time_share": {"contract": round(c_ms * 1e-3 / dt, 4), "measure": round(m_ms * 1e-3 / dt, 4),
+                       "pack": round(p_ms * 1e-3 / dt, 4)},
+    }
 
+
+def check_one_gpu(args):
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is design-only "
                                    "(samples shard by global index with no exchange)"}), flush=True)
         raise SystemExit(2)
 
+
+def run_chain_bench(args):
     import torch
     from paper_2512_20064_amd import mps
 
-    if not torch.cuda.is_available():
-        raise SystemExit("bench needs a GPU")
-    mps.load()
     t128, t64, d, chi, wname = build_chain(args)
-    dev = upload(t64)
+    dev = upload(t64, share=args.workload == "uneven")
+    del t64
     M = len(dev)
     seed = 1003
-    log(f"uploaded {M} sites, {sum(t.numel() * 8 for t in dev) / 2**30:.1f} GiB")
+    log(f"{M} sites on the device, {distinct_bytes(dev) / 2**30:.1f} GiB")
 
     if args.copy_calibration:
         src = torch.empty(args.copy_calibration * 2**20, dtype=torch.uint8, device="cuda")
@@ -163,11 +187,15 @@ def main():
         log(f"copy calibration: {args.copy_calibration} MiB device-to-device copy")
 
     def run_form(form, steps, warmup):
-        sampler = mps.Sampler(0, n_chunk=args.chunk, profile=not args.no_profile, precision=form)
+        sampler = mps.Sampler(0, n_chunk=args.chunk, profile=not args.no_profile, precision=form,
+                              graph=args.graph)
         step = [0]
+        # graph capture needs a stream of its own (not the legacy null stream)
+        gstream = torch.cuda.Stream() if args.graph else None
 
         def one_step():
-            r = sampler.sample(dev, args.chunk, seed, n_offset=step[0] * args.chunk, want_logp=True)
+            r = sampler.sample(dev, args.chunk, seed, n_offset=step[0] * args.chunk, want_logp=True,
+                               stream=gstream)
             step[0] += 1
             return r
 
@@ -191,20 +219,10 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         sampler.close()
-        out = {"value": args.chunk * M * steps / dt, "ms_per_step": dt / steps * 1e3, "dt": dt}
+        out = {"value": args.chunk * M * steps / dt, "ms_per_step": dt / steps * 1e3, "dt": dt,
+               "alg_tflops": c_fl / dt / 1e12}
         if not args.no_profile and c_ms > 0:
-            f = FORMS[form]
-            alg = (c_fl / c_n) / (c_ms / c_n * 1e-3) / 1e12
-            achieved = alg * f["mfma_per_alg"]
-            out["roofline"] = {
-                "bound": "mfma", "achieved": round(achieved, 2), "peak": f["peak"], "unit": "TFLOP/s",
-                "frac": round(achieved / f["peak"], 4), "traffic": traffic_for(form, args.chunk),
-                "kernel": f["kernel"], "algorithmic_tflops": round(alg, 2),
-                "mfma_products_per_complex_product": f["mfma_per_alg"],
-                "avg_launch_ms": round(c_ms / c_n, 4), "launches": c_n,
-                "time_share": {"contract": round(c_ms * 1e-3 / dt, 4), "measure": round(m_ms * 1e-3 / dt, 4),
-                               "pack": round(p_ms * 1e-3 / dt, 4)},
-            }
+            out["roofline"] = roofline_of(form, c_fl, c_n, c_ms, dt, m_ms, p_ms, args.chunk)
         return out
 
     main_res = run_form(args.precision, args.steps, args.warmup)
@@ -218,7 +236,7 @@ def main():
                         "frac": r.get("roofline", {}).get("frac")}
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and t128 is not None:
         log("timing the FP64 oracle on the host")
         cpu = cpu_baseline(t128, seed, args.cpu_samples, min(args.cpu_sites, M))
 
@@ -227,8 +245,9 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": FORMS[args.precision]["dtype"],
         "data": "synthetic",
-        "config": {"workload": wname, "sites": M, "d": 4, "chi": int(max(chi)), "samples_per_step": args.chunk,
-                   "precision": args.precision, "tensor_bytes": int(sum(t.numel() * 8 for t in dev))},
+        "config": {"workload": wname, "sites": M, "d": (4 if args.workload != "uneven" else "2..6"),
+                   "chi": int(max(chi)), "samples_per_step": args.chunk,
+                   "precision": args.precision, "tensor_bytes": distinct_bytes(dev)},
         "roofline": roof, "cpu_baseline": cpu,
     }
     if beside:
@@ -236,6 +255,204 @@ def main():
         if "fp32" in beside:
             rec["speedup_vs_fp32"] = round(value / beside["fp32"]["value"], 3)
     print(json.dumps(rec), flush=True)
+
+
+def run_stream_bench(args):
+    """64-site window at chi = 10^4 streamed from pinned host memory."""
+    import torch
+    from paper_2512_20064_amd import mps, synth
+
+    M, chi_max, kind = args.sites, args.chi, args.storage
+    dl = [4] * M
+    t0 = time.time()
+    sites, chi = synth.structured_chain(5, dl, chi_max, pool=args.pool, device="cuda")
+    host = {}
+    stored = []
+    for A in sites:
+        if id(A) not in host:
+            b = synth.compress_site_torch(A, kind)
+            h = torch.empty(b.numel(), dtype=torch.uint8, pin_memory=True)
+            h.copy_(b)
+            host[id(A)] = h
+            del b
+        stored.append(host[id(A)])
+    shapes = [(chi[k], 4, chi[k + 1]) for k in range(M)]
+    del sites
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    pinned = sum(h.numel() for h in host.values())
+    log(f"window of {M} sites built and compressed ({kind}) in {time.time() - t0:.1f}s; "
+        f"{pinned / 2**30:.1f} GiB pinned")
+    N, seed = args.samples, 2024
+
+    # plain host-to-device copy rate of the same pinned buffers
+    big = max(host.values(), key=lambda h: h.numel())
+    dst = torch.empty(big.numel(), dtype=torch.uint8, device="cuda")
+    dst.copy_(big, non_blocking=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        dst.copy_(big, non_blocking=True)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 3 * big.numel() / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del dst
+    log(f"pinned H2D copy alone: {copy_gbps:.1f} GB/s")
+
+    sampler = mps.Sampler(0, n_chunk=args.chunk, profile=True, precision=args.precision)
+    # warm-up over the window's first plateau site (same scratch and staging sizes)
+    first_plateau = next(k for k in range(M) if chi[k] == chi_max and chi[k + 1] == chi_max)
+    sampler.sample_stored(stored[:first_plateau + 1], shapes[:first_plateau + 1], kind, N, seed)
+    torch.cuda.synchronize()
+    log("warm-up done")
+    t0 = time.perf_counter()
+    sampler.sample_stored(stored, shapes, kind, N, seed)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = sampler.stats
+    sampler.close()
+    main_ms = st.contract_ms + st.measure_ms + st.pack_ms + st.expand_ms
+    copy_ms = st.h2d_ms
+    overlap = None
+    if copy_ms > 0:
+        overlap = max(0.0, min(1.0, (main_ms + copy_ms - dt * 1e3) / copy_ms))
+    rec = {
+        "metric": "site-samples/s, streamed chi=10^4 window", "value": round(N * M / dt, 1),
+        "unit": "site-samples/s", "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": round(dt * 1e3, 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": FORMS[args.precision]["dtype"], "data": "synthetic",
+        "config": {"workload": f"streamed window M={M} d=4 chi={chi_max} structured right-canonical, "
+                               f"{kind} in pinned host memory (pool of {args.pool} plateau tensors, every "
+                               f"site copied separately), N={N} in chunks of {args.chunk}",
+                   "sites": M, "chi": chi_max, "storage": kind, "samples": N, "precision": args.precision},
+        "stream": {
+            "per_site_ms": round(dt * 1e3 / M, 2),
+            "h2d_bytes": st.h2d_bytes,
+            "h2d_gbps_in_sweep": round(st.h2d_bytes / (copy_ms * 1e-3) / 1e9, 2) if copy_ms > 0 else None,
+            "h2d_gbps_copy_alone": round(copy_gbps, 2),
+            "copy_ms": round(copy_ms, 1), "compute_stream_ms": round(main_ms, 1),
+            "expand_ms": round(st.expand_ms, 1), "overlap": None if overlap is None else round(overlap, 4),
+            "copy_share_of_wall": round(copy_ms / (dt * 1e3), 4),
+        },
+        "roofline": (roofline_of(args.precision, st.contract_flops, st.contract_launches, st.contract_ms,
+                                 dt, st.measure_ms, st.pack_ms, args.chunk) if st.contract_ms > 0 else None),
+        "cpu_baseline": None,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+def run_batch_bench(args):
+    """256 independent chains in one batched call against one call per chain."""
+    import torch
+    from paper_2512_20064_amd import mps, synth
+
+    t0 = time.time()
+    specs = synth.ensemble_specs(seed=2, B=args.chains)
+    chains = []
+    for b, (Mb, db, cb) in enumerate(specs):
+        dl = [db] * Mb
+        t128 = synth.random_mps(7, dl, synth.ramp_bonds(dl, cb), mps_id=b, pool=4)
+        chains.append(upload(synth.to_c64(t128), share=True))
+    N, seed = args.samples, 77
+    tot_sites = sum(len(c) for c in chains)
+    flops = sum(8.0 * N * t.shape[0] * t.shape[1] * t.shape[2] for c in chains for t in c)
+    log(f"{len(chains)} chains, {tot_sites} sites, built in {time.time() - t0:.1f}s")
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+
+    res = {}
+    for form in [args.precision] + [f for f in args.beside.split(",") if f and f != args.precision]:
+        sb = mps.Sampler(0, n_chunk=args.chunk, precision=form)
+        t_batch = timed(lambda: sb.sample_batch(chains, N, seed), args.steps)
+        log(f"{form} batched: {t_batch * 1e3:.1f} ms")
+        singles = [mps.Sampler(0, n_chunk=args.chunk, precision=form, mps_id=b) for b in range(len(chains))]
+
+        def loop():
+            for b, c in enumerate(chains):
+                singles[b].sample(c, N, seed)
+
+        t_loop = timed(loop, args.steps)
+        log(f"{form} one call per chain: {t_loop * 1e3:.1f} ms")
+        for s_ in singles:
+            s_.close()
+        sb.close()
+        res[form] = {"batched": N * tot_sites / t_batch, "per_chain_calls": N * tot_sites / t_loop,
+                     "batched_ms": t_batch * 1e3, "per_chain_ms": t_loop * 1e3,
+                     "alg_tflops_batched": flops / t_batch / 1e12}
+    main = res[args.precision]
+    rec = {
+        "metric": "site-samples/s, batched ensemble", "value": round(main["batched"], 1), "unit": "site-samples/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": round(main["batched_ms"], 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": FORMS[args.precision]["dtype"],
+        "data": "synthetic",
+        "config": {"workload": f"{len(chains)} random right-canonical chains, M~U[32,512], chi in "
+                               f"{{16,32,64,128,256}}, d in {{2,3,4}}, complex64, N={N} each",
+                   "chains": len(chains), "total_sites": tot_sites, "samples": N, "precision": args.precision},
+        "batch": {f: {k: round(v, 3) for k, v in r.items()} for f, r in res.items()},
+        "speedup_batched_vs_per_chain": round(main["batched"] / main["per_chain_calls"], 3),
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+WORKLOAD_DEFAULTS = {
+    "resident": {"sites": 1024, "chi": 1024, "pool": 16, "chunk": 65536},
+    "small": {"sites": 32, "chi": 32, "pool": 1, "chunk": 4096},
+    "uneven": {"sites": 2048, "chi": 4096, "pool": 2, "chunk": 16384},
+    "stream": {"sites": 64, "chi": 10000, "pool": 4, "chunk": 65536, "samples": 1 << 17},
+    "batch": {"chunk": 8192, "samples": 8192},
+}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="resident", choices=sorted(WORKLOAD_DEFAULTS))
+    ap.add_argument("--sites", type=int, default=None)
+    ap.add_argument("--chi", type=int, default=None)
+    ap.add_argument("--pool", type=int, default=None)
+    ap.add_argument("--chunk", type=int, default=None)
+    ap.add_argument("--samples", type=int, default=None, help="samples per call (stream, batch)")
+    ap.add_argument("--chains", type=int, default=256, help="chains in the batch workload")
+    ap.add_argument("--storage", default="cf16", choices=["c64", "cf16", "cf8"], help="stream workload storage")
+    ap.add_argument("--precision", default="fp32", choices=sorted(FORMS))
+    ap.add_argument("--graph", type=int, default=0, help="replay one captured chunk graph per chunk")
+    ap.add_argument("--beside", default="", help="comma-separated forms also timed (e.g. fp32)")
+    ap.add_argument("--beside-steps", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-samples", type=int, default=1024)
+    ap.add_argument("--cpu-sites", type=int, default=512)
+    ap.add_argument("--no-profile", action="store_true", help="do not event-time each launch")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run one plain device copy of this many MiB (reference for HBM counters)")
+    args = ap.parse_args()
+    for k, v in WORKLOAD_DEFAULTS[args.workload].items():
+        if getattr(args, k) is None:
+            setattr(args, k, v)
+    check_one_gpu(args)
+
+    import torch
+    from paper_2512_20064_amd import mps
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench needs a GPU")
+    mps.load()
+    if args.workload == "stream":
+        run_stream_bench(args)
+    elif args.workload == "batch":
+        run_batch_bench(args)
+    else:
+        run_chain_bench(args)
 
 
 if __name__ == "__main__":

@@ -217,6 +217,39 @@ int mps_sample(mps_handle h, const void* const* tensors, int32_t dtype,
 int mps_sample_batch(mps_handle h, int32_t B, const mps_chain* chains, int32_t dtype,
                      int64_t N, int64_t n_offset, uint64_t seed);
 
+/* Result of mps_autotune. */
+typedef struct {
+  int64_t n_chunk;        /* chosen samples per chunk                               */
+  int32_t tile_group;     /* chosen contraction tile order (see mps_options)        */
+  int32_t probe_sites;    /* sites 0 .. probe_sites-1 formed the probe              */
+  int32_t candidates;     /* (n_chunk, tile_group) pairs timed                      */
+  int32_t skipped;        /* pairs skipped for lack of device memory                */
+  double rate;            /* probe site-samples/s of the chosen pair                */
+  double default_rate;    /* probe site-samples/s of the library defaults (0: not timed) */
+} mps_tune_report;
+
+/*
+ * Autotuner: pick n_chunk and tile_group for this chain shape and the
+ * handle's precision, and store them in the handle's options.
+ *
+ * The probe is the chain's prefix up to and including the first site of
+ * largest per-sample work chi[k]*d[k]*chi[k+1] (the plateau shape, which
+ * dominates the sweep, together with the ramp that leads to it).  Every pair
+ * of n_chunk in {8192, 16384, 32768, 65536, 131072, 262144} (capped at N)
+ * and tile_group in {1, 2, 4, 8} is timed as one warm-up and two timed
+ * single-chunk sweeps over the probe (wall clock around the synchronous
+ * call); pairs whose scratch cannot be allocated are skipped.  The pair
+ * with the highest site-samples/s wins.  Arguments as in mps_sample, with
+ * N the job size the handle will be used for (N >= 1); no outcomes are
+ * returned.  Debug emits, displacement, profiling and graph replay are off
+ * during the probe; the other options are restored afterwards.  The
+ * handle's scratch is released at the end (the next call allocates what the
+ * chosen chunk needs).  Returns MPS_OK, or an error as mps_sample.
+ */
+int mps_autotune(mps_handle h, const void* const* tensors, int32_t dtype,
+                 const int32_t* chi, const int32_t* d, int32_t M, int64_t N,
+                 uint64_t seed, mps_tune_report* rep);
+
 /* Counters of the last mps_sample / mps_sample_batch call on this handle. */
 int mps_get_stats(mps_handle h, mps_stats* st);
 

@@ -32,6 +32,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -597,6 +598,10 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
   if ((e = mps::launch_zero_int(nflag, 1, stream)) != hipSuccess) return hip_fail(e, "zero kernel");
 
   if (site_outer) {
+    // Both slot events start out recorded on the compute stream, so the first
+    // two copies wait for nothing but this call's own earlier work.
+    for (int i = 0; i < 2; ++i)
+      if ((e = hipEventRecord(h->ev_expand[i], stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     for (int64_t c = 0; c < nchunks && rc == MPS_OK; ++c) rc = run_init(c, chunk_tab + c, cargs[c].rows);
     if (rc == MPS_OK && host_site[0]) rc = stage_copy(0);
     for (int k = 0; k < Mmax && rc == MPS_OK; ++k) {
@@ -789,6 +794,121 @@ int mps_sample_batch(mps_handle h, int32_t B, const mps_chain* chains_in, int32_
     return MPS_OK;
   }
   return run_sweep(h, chains, N, n_offset, seed, false, dtype);
+}
+
+int mps_autotune(mps_handle h, const void* const* tensors, int32_t dtype, const int32_t* chi, const int32_t* d,
+                 int32_t M, int64_t N, uint64_t seed, mps_tune_report* rep) {
+  int rc = check_call(h, dtype, N, 0);
+  if (rc) return rc;
+  if (!rep) return fail(MPS_EINVAL, "rep is NULL");
+  if (N < 1) return fail(MPS_EINVAL, "N = %lld < 1", (long long)N);
+  std::vector<Chain> chains(1);
+  chains[0] = Chain{tensors, chi, d, M, h->opt.mps_id, nullptr, nullptr, Shape{}};
+  if ((rc = validate_chain(chains[0], h->opt.precision, chains[0].sh, 0))) return rc;
+  // probe: the prefix up to the first site of largest per-sample work
+  int kp = 0;
+  double wmax = -1.0;
+  for (int k = 0; k < M; ++k) {
+    const double w = (double)chi[k] * d[k] * chi[k + 1];
+    if (w > wmax) {
+      wmax = w;
+      kp = k;
+    }
+  }
+  const int Mp = kp + 1;
+  chains[0].M = Mp;
+  if ((rc = validate_chain(chains[0], h->opt.precision, chains[0].sh, 0))) return rc;
+
+  const int64_t chunk_set[] = {8192, 16384, 32768, 65536, 131072, 262144};
+  const int group_set[] = {1, 2, 4, 8};
+  std::vector<int64_t> ncs;
+  for (int64_t c : chunk_set)
+    if (c <= N) ncs.push_back(c);
+  if (ncs.empty() || (ncs.back() < N && N < chunk_set[5])) ncs.push_back(std::min<int64_t>(N, chunk_set[5]));
+  const int64_t nmax = ncs.back();
+
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev == 0) return fail(MPS_ENODEV, "no HIP device available");
+  if (h->device >= ndev) return fail(MPS_ENODEV, "device %d not present (%d devices)", h->device, ndev);
+  if ((e = hipSetDevice(h->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  int32_t* outc = nullptr;
+  double* lp = nullptr;
+  if ((e = hipMalloc(&outc, (size_t)nmax * Mp * sizeof(int32_t))) != hipSuccess ||
+      (e = hipMalloc(&lp, (size_t)nmax * sizeof(double))) != hipSuccess) {
+    (void)hipGetLastError();
+    if (outc) (void)hipFree(outc);
+    return fail(MPS_ENOMEM, "autotune: probe outputs (%lld samples) do not fit", (long long)nmax);
+  }
+  chains[0].outcomes = outc;
+  chains[0].logp = lp;
+
+  const mps_options saved = h->opt;
+  mps_tune_report r{};
+  r.probe_sites = Mp;
+  int64_t best_nc = 0;
+  int best_g = 0;
+  double best = -1.0;
+  const int64_t def_nc = std::min<int64_t>(N, kDefaultChunk);
+  int err = MPS_OK;
+  for (int64_t nc : ncs) {
+    for (int g : group_set) {
+      h->opt = saved;
+      h->opt.n_chunk = nc;
+      h->opt.tile_group = g;
+      h->opt.profile = 0;
+      h->opt.graph = 0;
+      h->opt.emit_n = 0;
+      h->opt.emit_probs = nullptr;
+      h->opt.emit_u = nullptr;
+      h->opt.displace = nullptr;
+      int rr = run_sweep(h, chains, nc, 0, seed, true, dtype);
+      if (rr == MPS_ENOMEM) {
+        r.skipped++;
+        continue;
+      }
+      if (rr != MPS_OK && rr != MPS_ENUMERIC) {
+        err = rr;
+        break;
+      }
+      const auto t0 = std::chrono::steady_clock::now();
+      for (int rep_i = 0; rep_i < 2 && (rr == MPS_OK || rr == MPS_ENUMERIC); ++rep_i)
+        rr = run_sweep(h, chains, nc, 0, seed, true, dtype);
+      const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (rr != MPS_OK && rr != MPS_ENUMERIC) {
+        err = rr;
+        break;
+      }
+      const double rate = 2.0 * (double)nc * Mp / dt;
+      r.candidates++;
+      if (nc == def_nc && g == kDefaultGroup) r.default_rate = rate;
+      if (rate > best) {
+        best = rate;
+        best_nc = nc;
+        best_g = g;
+      }
+    }
+    if (err) break;
+  }
+  h->opt = saved;
+  (void)hipFree(outc);
+  (void)hipFree(lp);
+  if (h->scratch) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(h->scratch);
+    h->scratch = nullptr;
+    h->scratch_bytes = 0;
+  }
+  if (err) return err;
+  if (best_nc == 0) return fail(MPS_ENOMEM, "autotune: no candidate chunk fits in device memory");
+  h->opt.n_chunk = best_nc;
+  h->opt.tile_group = best_g;
+  r.n_chunk = best_nc;
+  r.tile_group = best_g;
+  r.rate = best;
+  *rep = r;
+  g_err.clear();
+  return MPS_OK;
 }
 
 }  // extern "C"

@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "MPS_OK", -1: "MPS_EINVAL", -2: "MPS_ENOMEM", -3: "MPS_ENODEV
                 -4: "MPS_EHIP", -5: "MPS_ENUMERIC"}
 
 EXPORTS = ("mps_options_init", "mps_create", "mps_set_options", "mps_sample", "mps_sample_batch",
-           "mps_get_stats", "mps_last_error", "mps_destroy")
+           "mps_autotune", "mps_get_stats", "mps_last_error", "mps_destroy")
 
 
 class mps_options(ctypes.Structure):
@@ -80,6 +80,18 @@ class mps_stats(ctypes.Structure):
     ]
 
 
+class mps_tune_report(ctypes.Structure):
+    _fields_ = [
+        ("n_chunk", ctypes.c_int64),
+        ("tile_group", ctypes.c_int32),
+        ("probe_sites", ctypes.c_int32),
+        ("candidates", ctypes.c_int32),
+        ("skipped", ctypes.c_int32),
+        ("rate", ctypes.c_double),
+        ("default_rate", ctypes.c_double),
+    ]
+
+
 class MPSError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
@@ -111,6 +123,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mps_sample_batch.argtypes = [P, ctypes.c_int32, ctypes.POINTER(mps_chain), ctypes.c_int32, ctypes.c_int64,
                                      ctypes.c_int64, ctypes.c_uint64]
     lib.mps_sample_batch.restype = ctypes.c_int
+    lib.mps_autotune.argtypes = [P, ctypes.POINTER(P), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                                 ctypes.POINTER(mps_tune_report)]
+    lib.mps_autotune.restype = ctypes.c_int
     lib.mps_get_stats.argtypes = [P, ctypes.POINTER(mps_stats)]
     lib.mps_get_stats.restype = ctypes.c_int
     lib.mps_last_error.argtypes = []
@@ -158,6 +174,16 @@ def mps_sample(h, tensor_ptrs, dtype: int, chi, d, M: int, N: int, n_offset: int
     return load().mps_sample(h, arr, dtype, chi_a, d_a, M, N, n_offset, ctypes.c_uint64(seed),
                              ctypes.c_void_p(outcomes_ptr) if outcomes_ptr else None,
                              ctypes.c_void_p(logp_ptr) if logp_ptr else None)
+
+
+def mps_autotune(h, tensor_ptrs, dtype: int, chi, d, M: int, N: int, seed: int):
+    """Raw call; returns (status, mps_tune_report)."""
+    arr = (ctypes.c_void_p * len(tensor_ptrs))(*[ctypes.c_void_p(int(p)) if p else None for p in tensor_ptrs])
+    chi_a = (ctypes.c_int32 * len(chi))(*[int(x) for x in chi])
+    d_a = (ctypes.c_int32 * len(d))(*[int(x) for x in d])
+    rep = mps_tune_report()
+    rc = load().mps_autotune(h, arr, dtype, chi_a, d_a, M, N, ctypes.c_uint64(seed), ctypes.byref(rep))
+    return rc, rep
 
 
 def make_chain(tensor_ptrs, chi, d, mps_id: int, outcomes_ptr: int, logp_ptr: int | None):
@@ -269,6 +295,44 @@ class Sampler:
             out["probs"] = emit_probs
             out["u"] = emit_u
         return out
+
+    def autotune(self, tensors, N: int, seed: int = 0, stream=None, cache: str | None = None) -> dict:
+        """Pick n_chunk and tile_group for this chain shape (mps_autotune) and
+        keep them for later calls.  cache: optional JSON file; an entry for
+        the same (precision, N, chi, d) is reused instead of timing again."""
+        import hashlib
+        import json
+        import torch
+        M = len(tensors)
+        chi = [int(tensors[0].shape[0])] + [int(t.shape[2]) for t in tensors]
+        d = [int(t.shape[1]) for t in tensors]
+        for t in tensors:
+            if t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("site tensors must be contiguous complex64 CUDA tensors")
+        key = "%d:%d:%s" % (self.opt.precision, N, hashlib.sha256(repr((chi, d)).encode()).hexdigest()[:16])
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+            if key in table:
+                self.opt.n_chunk = int(table[key]["n_chunk"])
+                self.opt.tile_group = int(table[key]["tile_group"])
+                return dict(table[key], cached=True)
+        opt = mps_options.from_buffer_copy(self.opt)
+        s = stream if stream is not None else torch.cuda.current_stream(torch.device("cuda", self.device))
+        opt.stream = s.cuda_stream
+        mps_set_options(self.h, opt)
+        rc, rep = mps_autotune(self.h, [t.data_ptr() for t in tensors], MPS_C64, chi, d, M, N, seed)
+        if rc:
+            raise MPSError(rc, mps_last_error())
+        self.opt.n_chunk = rep.n_chunk
+        self.opt.tile_group = rep.tile_group
+        out = {name: getattr(rep, name) for name, _ in mps_tune_report._fields_}
+        if cache:
+            table[key] = out
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+        return dict(out, cached=False)
 
     def sample_batch(self, chains, N: int, seed: int, n_offset: int = 0, want_logp: bool = True, stream=None,
                      raise_numeric: bool = False):

@@ -281,3 +281,116 @@ def compressed_bytes(chi_l: int, d: int, chi_r: int, kind: str) -> int:
         return 4 * n
     nb = -(-chi_l // FP8_BLOCK) * -(-(d * chi_r) // FP8_BLOCK)
     return -(-2 * n // 256) * 256 + 4 * nb
+
+
+# --------------------------------------------------------------------------
+# Large-bond workloads (chi in the thousands).  A QR of a chi x d*chi matrix
+# per distinct tensor takes minutes to hours on the host at these sizes, so
+# these tensors are built directly with orthonormal rows from discrete
+# Fourier rows with random phases, on any torch device:
+#
+# * chi_l <= chi_r:  B[:, i, :] = c_i * diag(e^{i a_i}) F[:chi_l, :] diag(e^{i b_i}),
+#   F the unitary DFT of size chi_r, c_i proportional to exp(-i/2) with
+#   sum_i c_i^2 = 1; rows of F are orthonormal, so sum_i B_i B_i^H = I and
+#   branch i carries weight c_i^2 (the decaying photon-number profile);
+# * chi_l > chi_r (right end of a ramp, chi_l <= d*chi_r):
+#   B.reshape(chi_l, d*chi_r) = diag(e^{i a}) F[:chi_l, :] diag(e^{i b}),
+#   F the unitary DFT of size d*chi_r.
+#
+# The phases come from PCG64 seeded like the Gaussian sites, so a tensor is
+# the same on every device up to the rounding of the phase evaluation.
+# --------------------------------------------------------------------------
+
+def _dft_rows(torch, rows: int, n: int, pa, pb, device):
+    """diag(e^{i pa}) F_n[:rows, :] diag(e^{i pb}) as complex64 (rows x n)."""
+    import math
+    r = torch.arange(rows, device=device, dtype=torch.int64)
+    c = torch.arange(n, device=device, dtype=torch.int64)
+    ang = torch.remainder(r[:, None] * c[None, :], n).to(torch.float64) * (-2.0 * math.pi / n)
+    ang += torch.as_tensor(pa, device=device)[:, None]
+    ang += torch.as_tensor(pb, device=device)[None, :]
+    mag = torch.full_like(ang, 1.0 / math.sqrt(n))
+    return torch.polar(mag, ang).to(torch.complex64)
+
+
+def structured_site(seed_words: list[int], chi_l: int, d: int, chi_r: int, device="cpu"):
+    """Right-canonical complex64 torch tensor (chi_l, d, chi_r) without a QR."""
+    import torch
+    assert chi_l <= d * chi_r
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(w) for w in seed_words] + [0x5D])))
+    two_pi = 2.0 * np.pi
+    if chi_l <= chi_r:
+        c = np.exp(-0.5 * np.arange(d))
+        c /= np.sqrt(np.sum(c * c))
+        out = torch.empty((chi_l, d, chi_r), dtype=torch.complex64, device=device)
+        for i in range(d):
+            pa = rng.uniform(0, two_pi, chi_l)
+            pb = rng.uniform(0, two_pi, chi_r)
+            out[:, i, :] = _dft_rows(torch, chi_l, chi_r, pa, pb, device) * float(c[i])
+        return out
+    pa = rng.uniform(0, two_pi, chi_l)
+    pb = rng.uniform(0, two_pi, d * chi_r)
+    return _dft_rows(torch, chi_l, d * chi_r, pa, pb, device).reshape(chi_l, d, chi_r)
+
+
+def structured_chain(tensor_seed: int, d: list[int], chi_max: int, pool: int = 4, device="cpu"):
+    """Chain of structured sites with ramped bonds; a repeated shape cycles
+    over ``pool`` distinct tensors (shared references).  Returns
+    (tensors, chi)."""
+    chi = ramp_bonds(d, chi_max)
+    cache: dict[tuple, object] = {}
+    sites = []
+    for k in range(len(d)):
+        shape = (chi[k], d[k], chi[k + 1])
+        key = shape + (k % pool,)
+        if key not in cache:
+            cache[key] = structured_site([tensor_seed, _POOL_TAG, *key], *shape, device=device)
+        sites.append(cache[key])
+    return sites, chi
+
+
+def compress_site_torch(A, kind: str):
+    """compress_site for a complex64 torch tensor on any device (same bytes:
+    binary16 by torch's round-to-nearest-even cast, E4M3 by the same
+    nearest-even search over the code values as encode_e4m3, block scales
+    formed in float64 and rounded to float32 once)."""
+    import torch
+    A = A.contiguous()
+    chi_l, d, chi_r = A.shape
+    ri = torch.view_as_real(A)
+    if kind == "c64":
+        return ri.reshape(-1).view(torch.uint8).clone()
+    if kind == "cf16":
+        return ri.to(torch.float16).reshape(-1).view(torch.uint8).clone()
+    if kind != "cf8":
+        raise ValueError(kind)
+    ncol = d * chi_r
+    mat = ri.reshape(chi_l, ncol, 2)
+    nbr, nbc = -(-chi_l // FP8_BLOCK), -(-ncol // FP8_BLOCK)
+    n = chi_l * ncol
+    off = -(-2 * n // 256) * 256
+    out = torch.zeros(off + 4 * nbr * nbc, dtype=torch.uint8, device=A.device)
+    codes = out[:2 * n].view(chi_l, ncol, 2)
+    scales = torch.empty((nbr, nbc), dtype=torch.float32, device=A.device)
+    pos = torch.as_tensor(E4M3_VALUES[:0x7F], device=A.device)
+    for bi in range(nbr):
+        rows = slice(bi * FP8_BLOCK, min(chi_l, (bi + 1) * FP8_BLOCK))
+        slab = mat[rows]                                         # (r, ncol, 2)
+        r = slab.shape[0]
+        padc = nbc * FP8_BLOCK - ncol
+        amax = torch.nn.functional.pad(slab.abs().amax(dim=2), (0, padc)).view(r, nbc, FP8_BLOCK).amax(dim=(0, 2))
+        sc = torch.where(amax > 0, (amax.to(torch.float64) / E4M3_MAX).to(torch.float32),
+                         torch.ones_like(amax))
+        scales[bi] = sc
+        scol = sc.repeat_interleave(FP8_BLOCK)[:ncol].to(torch.float64)
+        x = torch.clamp(slab.to(torch.float64) / scol[None, :, None], -E4M3_MAX, E4M3_MAX)
+        a = x.abs()
+        idx = torch.clamp(torch.searchsorted(pos, a), 1, pos.numel() - 1)
+        lo, hi = pos[idx - 1], pos[idx]
+        pick_hi = (a - lo > hi - a) | ((a - lo == hi - a) & (idx % 2 == 0))
+        code = torch.where(pick_hi, idx, idx - 1)
+        code = torch.where(a == 0, torch.zeros_like(code), code)
+        code = torch.where(x < 0, code | 0x80, code)
+        codes[rows] = code.to(torch.uint8)
+    out[off:] = scales.reshape(-1).view(torch.uint8)
+    return out

@@ -40,6 +40,7 @@ def test_options_struct_matches_header():
     # the binding's struct must have the header's size (8-byte aligned fields)
     assert ctypes.sizeof(mps.mps_options) == 4 + 4 + 8 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8 + 4 + 4 + 8
     assert ctypes.sizeof(mps.mps_stats) == 15 * 8
+    assert ctypes.sizeof(mps.mps_tune_report) == 8 + 4 * 4 + 8 + 8
 
 
 def _call(h, **kw):
@@ -142,5 +143,29 @@ def test_batch_validation_on_host():
         assert mps.load().mps_sample_batch(h, 0, None, mps.MPS_C64, 10, 0, 1) == mps.MPS_EINVAL
         assert mps.mps_sample_batch(h, [good], 9, 10, 0, 1) == mps.MPS_EINVAL  # dtype
         assert mps.mps_sample_batch(h, [good], mps.MPS_C64, 0, 0, 1) == mps.MPS_OK  # empty
+    finally:
+        mps.mps_destroy(h)
+
+
+def test_autotune_validates_on_host():
+    h = mps.mps_create(0)
+    try:
+        ptrs, chi, d = [1, 1], [1, 4, 1], [4, 4]
+        rc, _ = mps.mps_autotune(h, ptrs, mps.MPS_C64, chi, d, 2, 0, 1)  # N = 0
+        assert rc == mps.MPS_EINVAL
+        rc, _ = mps.mps_autotune(h, ptrs, mps.MPS_C64, [2, 4, 1], d, 2, 100, 1)  # chi[0] != 1
+        assert rc == mps.MPS_EINVAL and "chi[0]" in mps.mps_last_error()
+        rc = mps.load().mps_autotune(h, None, 0, None, None, 2, 100, 1, None)
+        assert rc == mps.MPS_EINVAL
+    finally:
+        mps.mps_destroy(h)
+
+
+@pytest.mark.skipif(_gpu_present(), reason="checks the no-device path")
+def test_autotune_reports_enodev_without_gpu():
+    h = mps.mps_create(0)
+    try:
+        rc, _ = mps.mps_autotune(h, [1, 1], mps.MPS_C64, [1, 4, 1], [4, 4], 2, 100, 1)
+        assert rc == mps.MPS_ENODEV
     finally:
         mps.mps_destroy(h)

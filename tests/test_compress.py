@@ -95,3 +95,22 @@ def test_cf16_is_numpy_binary16_and_c64_is_identity():
     assert np.array_equal(dec.imag, A.imag.astype(np.float16).astype(np.float64))
     assert np.array_equal(decode_site(synth.compress_site(A, "c64"), A.shape, "c64"), A.astype(np.complex128))
     assert synth.compressed_bytes(20, 4, 33, "cf16") == 4 * 20 * 4 * 33
+
+
+@pytest.mark.parametrize("shape", [(130, 3, 50), (64, 4, 64), (257, 2, 170), (1, 4, 4)])
+def test_structured_sites_are_right_canonical_and_torch_compression_matches(shape):
+    """Large-bond generator: orthonormal rows (sum_i B_i B_i^H = I within
+    complex64 rounding), branch weights c_i^2 ~ exp(-i) where chi_l <= chi_r,
+    and the torch compressor writes the same bytes as the numpy one."""
+    torch = pytest.importorskip("torch")
+    B = synth.structured_site([1, 2], *shape)
+    assert B.dtype == torch.complex64 and tuple(B.shape) == shape
+    Bn = B.numpy().astype(np.complex128)
+    assert synth.canonical_error(Bn) < 1e-6
+    chi_l, d, chi_r = shape
+    if chi_l <= chi_r:
+        w = np.array([np.sum(np.abs(Bn[:, i, :]) ** 2) / chi_l for i in range(d)])
+        c = np.exp(-np.arange(d)) / np.sum(np.exp(-np.arange(d)))
+        assert np.allclose(w, c, atol=1e-6)
+    for kind in ("c64", "cf16", "cf8"):
+        assert np.array_equal(synth.compress_site(B.numpy(), kind), synth.compress_site_torch(B, kind).numpy()), kind
