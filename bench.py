@@ -8,10 +8,11 @@ GBS-shaped resident chain, M = 1024 sites, d = 4, chi = 1024 (bond ramp
 (one device buffer per site, 32 GiB), 65536 samples per step; step s draws
 global samples [s*65536, (s+1)*65536) of the N = 2^20 job.
 
-Prints one JSON line: site-samples/s, the contraction kernel against the
-MFMA roofline of its operand type (event-timed live over the timed region),
-and the FP64 oracle timed on the host cores on a bounded sample of the same
-chain.
+Prints one JSON line: site-samples/s of the split-precision form (bf16 hi+lo,
+three MFMA products, within 1e-3 of the FP64 oracle), the contraction kernel
+against the MFMA roofline of its operand type (event-timed live over the
+timed region), the plain FP32 path timed beside it, and the FP64 oracle timed
+on the host cores on a bounded sample of the same chain.
 
 Other workloads (one JSON line each, not the headline):
   --workload uneven   M = 2048, d_k in {2..6}, chi_k = min(prod d, 4096),
@@ -404,11 +405,12 @@ def run_batch_bench(args):
 
 
 WORKLOAD_DEFAULTS = {
-    "resident": {"sites": 1024, "chi": 1024, "pool": 16, "chunk": 65536},
-    "small": {"sites": 32, "chi": 32, "pool": 1, "chunk": 4096},
-    "uneven": {"sites": 2048, "chi": 4096, "pool": 2, "chunk": 16384},
-    "stream": {"sites": 64, "chi": 10000, "pool": 4, "chunk": 65536, "samples": 1 << 17},
-    "batch": {"chunk": 8192, "samples": 8192},
+    "resident": {"sites": 1024, "chi": 1024, "pool": 16, "chunk": 65536, "precision": "bf16x3", "beside": "fp32"},
+    "small": {"sites": 32, "chi": 32, "pool": 1, "chunk": 4096, "precision": "fp32", "beside": ""},
+    "uneven": {"sites": 2048, "chi": 4096, "pool": 2, "chunk": 16384, "precision": "bf16x3", "beside": ""},
+    "stream": {"sites": 64, "chi": 10000, "pool": 4, "chunk": 65536, "samples": 1 << 17, "precision": "bf16x3",
+               "beside": ""},
+    "batch": {"chunk": 8192, "samples": 8192, "precision": "fp32", "beside": ""},
 }
 
 
@@ -425,9 +427,9 @@ def main():
     ap.add_argument("--samples", type=int, default=None, help="samples per call (stream, batch)")
     ap.add_argument("--chains", type=int, default=256, help="chains in the batch workload")
     ap.add_argument("--storage", default="cf16", choices=["c64", "cf16", "cf8"], help="stream workload storage")
-    ap.add_argument("--precision", default="fp32", choices=sorted(FORMS))
+    ap.add_argument("--precision", default=None, choices=sorted(FORMS))
     ap.add_argument("--graph", type=int, default=0, help="replay one captured chunk graph per chunk")
-    ap.add_argument("--beside", default="", help="comma-separated forms also timed (e.g. fp32)")
+    ap.add_argument("--beside", default=None, help="comma-separated forms also timed ('' for none)")
     ap.add_argument("--beside-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=1024)

@@ -28,6 +28,30 @@ EXPORTS = ("mps_options_init", "mps_create", "mps_set_options", "mps_sample", "m
            "mps_autotune", "mps_get_stats", "mps_last_error", "mps_destroy")
 
 
+def stored_bytes(kind: str, chi_l: int, d: int, chi_r: int) -> int:
+    """Bytes of one site tensor in a storage form (layouts in include/mps.h)."""
+    n = chi_l * d * chi_r
+    if kind == "c64":
+        return 8 * n
+    if kind == "cf16":
+        return 4 * n
+    if kind == "cf8":
+        nb = -(-chi_l // 128) * -(-(d * chi_r) // 128)
+        return -(-2 * n // 256) * 256 + 4 * nb
+    raise ValueError(kind)
+
+
+def _bonds(tensors):
+    """chi_0 .. chi_M of a list of (chi_k, d_k, chi_{k+1}) site tensors; the
+    shapes must chain (the library reads each tensor with these sizes)."""
+    for k, t in enumerate(tensors):
+        if t.dim() != 3:
+            raise ValueError(f"site {k}: expected a 3-d tensor (chi_l, d, chi_r)")
+        if k and int(t.shape[0]) != int(tensors[k - 1].shape[2]):
+            raise ValueError(f"site {k}: left bond {t.shape[0]} != right bond {tensors[k - 1].shape[2]} of site {k - 1}")
+    return [int(tensors[0].shape[0])] + [int(t.shape[2]) for t in tensors]
+
+
 class mps_options(ctypes.Structure):
     _fields_ = [
         ("precision", ctypes.c_int32),
@@ -259,7 +283,7 @@ class Sampler:
         import torch
         dev = torch.device("cuda", self.device)
         M = len(tensors)
-        chi = [int(tensors[0].shape[0])] + [int(t.shape[2]) for t in tensors]
+        chi = _bonds(tensors)
         d = [int(t.shape[1]) for t in tensors]
         for t in tensors:
             if t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous():
@@ -304,7 +328,7 @@ class Sampler:
         import json
         import torch
         M = len(tensors)
-        chi = [int(tensors[0].shape[0])] + [int(t.shape[2]) for t in tensors]
+        chi = _bonds(tensors)
         d = [int(t.shape[1]) for t in tensors]
         for t in tensors:
             if t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous():
@@ -348,7 +372,7 @@ class Sampler:
                 if t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous():
                     raise ValueError("site tensors must be contiguous complex64 CUDA tensors")
             M = len(tensors)
-            chi = [int(tensors[0].shape[0])] + [int(t.shape[2]) for t in tensors]
+            chi = _bonds(tensors)
             d = [int(t.shape[1]) for t in tensors]
             o = torch.empty((N, M), dtype=torch.int32, device=dev)
             lp = torch.empty((N,), dtype=torch.float64, device=dev) if want_logp else None
@@ -381,9 +405,16 @@ class Sampler:
         M = len(stored)
         chi = [int(shapes[0][0])] + [int(s[2]) for s in shapes]
         d = [int(s[1]) for s in shapes]
-        for t in stored:
+        if kind not in STORAGE or len(shapes) != M:
+            raise ValueError("kind must be one of %s and shapes must have one entry per site" % sorted(STORAGE))
+        for k, t in enumerate(stored):
             if t.dtype != torch.uint8 or not t.is_contiguous() or not (t.is_cuda or t.is_pinned()):
                 raise ValueError("stored sites must be contiguous uint8 tensors on the GPU or in pinned memory")
+            need = stored_bytes(kind, *[int(x) for x in shapes[k]])
+            if t.numel() < need:
+                raise ValueError(f"site {k}: {t.numel()} bytes stored, {kind} of shape {tuple(shapes[k])} needs {need}")
+            if k + 1 < M and int(shapes[k][2]) != int(shapes[k + 1][0]):
+                raise ValueError(f"site {k}: right bond {shapes[k][2]} != left bond of site {k + 1}")
         outcomes = torch.empty((N, M), dtype=torch.int32, device=dev)
         logp = torch.empty((N,), dtype=torch.float64, device=dev)
         emit_probs = emit_u = None
