@@ -71,9 +71,23 @@ struct LWriter;
 template <>
 struct LWriter<kOutF32> {
   float2* dst;
-  __device__ LWriter(const MeasureProb& a, int row) : dst(a.Lout + (size_t)row * a.chi_r) {}
+  int n;
+  __device__ LWriter(const MeasureProb& a, int row) : dst(a.Lout + (size_t)row * a.chi_r), n(a.chi_r) {}
   __device__ void put(int r, float x, float y) { dst[r] = make_float2(x, y); }
+  // complex r4 .. r4+3 (r4 a multiple of 4; entries at or past chi_r are dropped)
+  __device__ void put4(int r4, const float2 (&v)[4]) {
+    if (r4 + 4 <= n && (n & 1) == 0) {
+      float4* d4 = reinterpret_cast<float4*>(dst + r4);  // 16-byte aligned: row pitch and r4 are even
+      d4[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+      d4[1] = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (r4 + j < n) dst[r4 + j] = v[j];
+    }
+  }
   __device__ void pad(const MeasureProb&, int) {}
+  __device__ void pad_from(int, int) {}
 };
 
 template <>
@@ -93,11 +107,33 @@ struct LWriter<kOutBf16x2> {
     hi[w] = pack2(xh, yh);
     lo[w] = pack2(xl, yl);
   }
+  // complex r4 .. r4+3 (r4 a multiple of 4, zeros past chi_r): K values
+  // 2*r4 .. 2*r4+7, half of one 16-K block, one 16-byte store per plane.
+  __device__ void put4(int r4, const float2 (&v)[4]) {
+    uint32_t h[4], l[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bf16_t xh = (bf16_t)v[j].x, yh = (bf16_t)v[j].y;
+      h[j] = pack2(xh, yh);
+      l[j] = pack2((bf16_t)(v[j].x - (float)xh), (bf16_t)(v[j].y - (float)yh));
+    }
+    const size_t w = kblk_off(row, 2 * r4, ld) >> 1;
+    *reinterpret_cast<uint4*>(hi + w) = make_uint4(h[0], h[1], h[2], h[3]);
+    *reinterpret_cast<uint4*>(lo + w) = make_uint4(l[0], l[1], l[2], l[3]);
+  }
   __device__ void pad(const MeasureProb& a, int lane) {
     for (int k = 2 * a.chi_r + 2 * lane; k < ld; k += 128) {
       const size_t w = kblk_off(row, k, ld) >> 1;
       hi[w] = 0u;
       lo[w] = 0u;
+    }
+  }
+  // zeros for K in [k0, ld), k0 a multiple of 8
+  __device__ void pad_from(int k0, int lane) {
+    for (int k = k0 + 8 * lane; k < ld; k += 512) {
+      const size_t w = kblk_off(row, k, ld) >> 1;
+      *reinterpret_cast<uint4*>(hi + w) = make_uint4(0u, 0u, 0u, 0u);
+      *reinterpret_cast<uint4*>(lo + w) = make_uint4(0u, 0u, 0u, 0u);
     }
   }
   static __device__ uint32_t pack2(bf16_t a, bf16_t b) {
@@ -116,8 +152,21 @@ struct LWriter<kOutF16> {
     hi[kblk_off(row, 2 * r, ld) >> 1] =
         (uint32_t)__builtin_bit_cast(uint16_t, xh) | ((uint32_t)__builtin_bit_cast(uint16_t, yh) << 16);
   }
+  __device__ void put4(int r4, const float2 (&v)[4]) {
+    uint32_t h[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const f16_t xh = (f16_t)v[j].x, yh = (f16_t)v[j].y;
+      h[j] = (uint32_t)__builtin_bit_cast(uint16_t, xh) | ((uint32_t)__builtin_bit_cast(uint16_t, yh) << 16);
+    }
+    *reinterpret_cast<uint4*>(hi + (kblk_off(row, 2 * r4, ld) >> 1)) = make_uint4(h[0], h[1], h[2], h[3]);
+  }
   __device__ void pad(const MeasureProb& a, int lane) {
     for (int k = 2 * a.chi_r + 2 * lane; k < ld; k += 128) hi[kblk_off(row, k, ld) >> 1] = 0u;
+  }
+  __device__ void pad_from(int k0, int lane) {
+    for (int k = k0 + 8 * lane; k < ld; k += 512)
+      *reinterpret_cast<uint4*>(hi + (kblk_off(row, k, ld) >> 1)) = make_uint4(0u, 0u, 0u, 0u);
   }
 };
 
@@ -155,7 +204,9 @@ __device__ inline float2 displacement_entry(double mr, double mi, int i, int j) 
   return make_float2((float)(g * sr), (float)(g * si));
 }
 
-template <int OUT>
+// DISP: the launch's problems carry a displacement (mu != NULL).  A separate
+// instantiation keeps the displaced path's registers out of the plain one.
+template <int OUT, bool DISP>
 __global__ __launch_bounds__(256) void measure_kernel(const MeasureProb* probs, const ChunkArgs* chp, uint64_t seed,
                                                       int* nflag) {
   __shared__ float2 Dsh[4][DMAX * DMAX];  // displacement operator of each wave's sample
@@ -168,10 +219,10 @@ __global__ __launch_bounds__(256) void measure_kernel(const MeasureProb* probs, 
   const int64_t crow = ch.c0 + row;  // row within the call
   double* const logp = a.logp + (a.logp_in_call ? crow : row);
   const int d = a.d, T = a.T;
-  const bool disp = a.mu != nullptr;
+  const bool disp = DISP && a.mu != nullptr;
   const float2* Wrow = a.W + (size_t)row * d * a.chi_r;
 
-  double q[DMAX], P[DMAX];
+  double q[DMAX];
   if (!disp) {
     // branch weights from the contraction's partial sums
     const float* qp = a.qpart + (size_t)row * (d * T);
@@ -220,16 +271,11 @@ __global__ __launch_bounds__(256) void measure_kernel(const MeasureProb* probs, 
       q[i] = i < d ? v : 0.0;
     }
   }
-  double acc = 0.0;
-#pragma unroll
-  for (int i = 0; i < DMAX; ++i) {
-    acc += q[i];  // left-to-right prefix sums
-    P[i] = acc;
-  }
+  // S = P_{d-1}, the last of the left-to-right prefix sums P_j = q_0 + .. + q_j
   double S = 0.0;
 #pragma unroll
   for (int i = 0; i < DMAX; ++i)
-    if (i == d - 1) S = P[i];
+    if (i < d) S += q[i];
 
   const double lp_prev = *logp;
   const bool alive = !(lp_prev == -INFINITY);
@@ -240,9 +286,12 @@ __global__ __launch_bounds__(256) void measure_kernel(const MeasureProb* probs, 
   const double u = ((double)(x >> 12) + 0.5) * 0x1p-52;
 
   int s = 0;
+  double Pi = 0.0;
 #pragma unroll
-  for (int i = 0; i < DMAX; ++i)
-    if (i < d && u > P[i] / S) ++s;  // C_i = P_i / S;  C_{d-1} == 1
+  for (int i = 0; i < DMAX; ++i) {
+    Pi += q[i];                       // P_i, summed in the same order as S
+    if (i < d && u > Pi / S) ++s;     // C_i = P_i / S;  C_{d-1} == 1
+  }
   if (s > d - 1) s = d - 1;
   double qs = 0.0;
 #pragma unroll
@@ -269,11 +318,31 @@ __global__ __launch_bounds__(256) void measure_kernel(const MeasureProb* probs, 
   const float2* src = Wrow + (size_t)s * a.chi_r;
   LWriter<OUT> out(a, row);
   if (ok && !disp) {
+    // Each lane takes 4 consecutive complex of the chosen branch (zeros past
+    // chi_r), so the 16-bit formats get whole 16-byte stores.
     const float scale = (float)(1.0 / sqrt(qs));
-    for (int r = lane; r < a.chi_r; r += 64) {
-      const float2 w = src[r];
-      out.put(r, w.x * scale, w.y * scale);
+    const int nq = (a.chi_r + 3) >> 2;
+    const bool even = (a.chi_r & 1) == 0;  // src is then 16-byte aligned at every even r
+#pragma unroll 2
+    for (int q4 = lane; q4 < nq; q4 += 64) {
+      const int r4 = 4 * q4;
+      float2 v[4];
+      if (even && r4 + 4 <= a.chi_r) {
+        const float4 p0 = *reinterpret_cast<const float4*>(src + r4);
+        const float4 p1 = *reinterpret_cast<const float4*>(src + r4 + 2);
+        v[0] = make_float2(p0.x, p0.y);
+        v[1] = make_float2(p0.z, p0.w);
+        v[2] = make_float2(p1.x, p1.y);
+        v[3] = make_float2(p1.z, p1.w);
+      } else {
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) v[jj] = r4 + jj < a.chi_r ? src[r4 + jj] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) v[jj] = make_float2(v[jj].x * scale, v[jj].y * scale);
+      out.put4(r4, v);
     }
+    out.pad_from(8 * nq, lane);
   } else if (ok) {
     // chosen branch of W' = D(mu) W
     const float scale = (float)(1.0 / sqrt(qs));
@@ -349,16 +418,25 @@ hipError_t launch_zero_int(int* p, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int OUT>
+void launch_measure_t(bool displaced, dim3 grid, const MeasureProb* probs, const ChunkArgs* ch, uint64_t seed,
+                      int* nflag, hipStream_t s) {
+  if (displaced)
+    hipLaunchKernelGGL((measure_kernel<OUT, true>), grid, dim3(256), 0, s, probs, ch, seed, nflag);
+  else
+    hipLaunchKernelGGL((measure_kernel<OUT, false>), grid, dim3(256), 0, s, probs, ch, seed, nflag);
+}
+
 hipError_t launch_measure(int form, const MeasureProb* probs, int nprob, const ChunkArgs* ch, int grid_rows,
-                          uint64_t seed, int* nflag, hipStream_t s) {
+                          uint64_t seed, int* nflag, bool displaced, hipStream_t s) {
   if (grid_rows <= 0 || nprob <= 0) return hipSuccess;
   const dim3 grid((grid_rows + 3) / 4, nprob);
   if (form == 0)
-    hipLaunchKernelGGL(measure_kernel<kOutF32>, grid, dim3(256), 0, s, probs, ch, seed, nflag);
+    launch_measure_t<kOutF32>(displaced, grid, probs, ch, seed, nflag, s);
   else if (form == kBf16x3)
-    hipLaunchKernelGGL(measure_kernel<kOutBf16x2>, grid, dim3(256), 0, s, probs, ch, seed, nflag);
+    launch_measure_t<kOutBf16x2>(displaced, grid, probs, ch, seed, nflag, s);
   else
-    hipLaunchKernelGGL(measure_kernel<kOutF16>, grid, dim3(256), 0, s, probs, ch, seed, nflag);
+    launch_measure_t<kOutF16>(displaced, grid, probs, ch, seed, nflag, s);
   return hipGetLastError();
 }
 

@@ -482,6 +482,7 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
     return e2 == hipSuccess ? MPS_OK : hip_fail(e2, "hipEventRecord");
   };
   auto tp = [&](size_t off) { return (const void*)(dtab + off); };
+  const bool displaced = single && o.displace != nullptr;
 
 #define MPS_TRY(x)            \
   do {                        \
@@ -520,7 +521,7 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
     MPS_TRY(mark(k, 3, stream));
     MPS_TRY(mark(k, 4, stream));
     MPS_HIP(mps::launch_measure(form, (const mps::MeasureProb*)tp(sp.measure), sp.nprob, ch, grid_rows, seed, nflag,
-                                stream),
+                                displaced, stream),
             "measurement launch");
     return mark(k, 5, stream);
   };

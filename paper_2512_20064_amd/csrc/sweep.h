@@ -127,7 +127,8 @@ hipError_t launch_pack_lp(int form, const PackProb* probs, const int* blk_start,
                           hipStream_t s);
 hipError_t launch_contract_lp(int form, const ContractLpProb* probs, const int* tn_start, int nprob, int tn_total,
                               const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s);
+// displaced: the problems carry per-sample displacements (MeasureProb::mu)
 hipError_t launch_measure(int form, const MeasureProb* probs, int nprob, const ChunkArgs* ch, int grid_rows,
-                          uint64_t seed, int* nflag, hipStream_t s);
+                          uint64_t seed, int* nflag, bool displaced, hipStream_t s);
 
 }  // namespace mps
