@@ -114,7 +114,9 @@ constexpr int BM = kLpBM;            // rows (samples) per workgroup
 constexpr int BN = 2 * kLpBNC;       // real columns per workgroup
 constexpr int BK = kLpBK;            // real K per pipeline stage
 constexpr int NTHR = 512;            // 8 waves: 4 (rows) x 2 (columns)
-constexpr int NST = 4;               // pipeline stages in LDS
+constexpr int NST = 5;               // pipeline stages in LDS (5 x 32 KiB = the whole 160 KiB for bf16x3)
+constexpr int AHEAD = NST - 1;       // stages issued before the first one is read
+static_assert(AHEAD <= 4, "the shortest K (64 real values) has 4 stages");
 constexpr int ARR = BM * BK * 2;     // bytes of one operand tile in a stage (8 KiB)
 static_assert(BM == 256 && BN == 256 && BK == 16, "layout below assumes 256 x 256 x 16");
 
@@ -128,13 +130,11 @@ __device__ inline int lds_off(int row, int chunk) { return row * 32 + ((chunk ^ 
 // operations (n < 16) and nothing else.
 constexpr unsigned vmcnt_imm(unsigned n) { return (n & 0xF) | (0x7u << 4) | (0xFu << 8); }
 
-// Pipeline: stage kt lives in LDS buffer kt % 4.  Operand tiles go straight
+// Pipeline: stage kt lives in LDS buffer kt % NST.  Operand tiles go straight
 // from memory into LDS (global_load_lds_dwordx4: no staging registers and no
-// LDS store phase), three stages ahead of the MFMAs.  At the top of stage kt
-// each wave waits for its own loads of stage kt (later stages stay in
-// flight), then one barrier makes every wave's data visible and guarantees
-// that every wave is done with stage kt-1, whose buffer the loads of stage
-// kt+3 then overwrite.
+// LDS store phase), two to three stages ahead of the stage being read from
+// LDS, which is itself one stage ahead of the MFMAs (see open_stage below).
+// One stage of MFMAs is ~1500 cycles per SIMD.
 template <typename T, int NPROD>
 __global__ __launch_bounds__(NTHR, 1) void contract_lp_kernel(const ContractLpProb* probs, const int* tn_start,
                                                              int nprob, int tn_total, int tiles_m, int per_xcd,
@@ -198,41 +198,72 @@ __global__ __launch_bounds__(NTHR, 1) void contract_lp_kernel(const ContractLpPr
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = zero;
 
-  const int nkt = a.Kp / BK;  // >= 4: Kp is a multiple of 64
-  issue(0);
-  issue(1);
-  issue(2);
-  for (int kt = 0; kt < nkt; ++kt) {
-    const int later = min(2, nkt - 1 - kt);
-    if (later == 2) __builtin_amdgcn_s_waitcnt(vmcnt_imm(2 * IPW));
-    else if (later == 1) __builtin_amdgcn_s_waitcnt(vmcnt_imm(IPW));
-    else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
-    asm volatile("s_barrier" ::: "memory");
-    if (kt + 3 < nkt) issue(kt + 3);
-    const char* st = lds + (kt % NST) * STAGE;
+  // The operands of one stage, read from LDS into registers.  Two sets
+  // alternate: while the MFMAs of stage kt run on one set, the LDS reads of
+  // stage kt+1 fill the other, so LDS time hides behind MFMA time instead of
+  // adding to it.
+  struct Ops {
     V8 ah[2], al[2], bh[4], bl[4];
+  };
+  auto lds_read = [&](int kt, Ops& o) {
+    const char* st = lds + (kt % NST) * STAGE;
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) {
       const int row = wr + rb * 32 + j;
-      ah[rb] = *reinterpret_cast<const V8*>(st + 0 * ARR + lds_off(row, half));
-      if (NPROD == 3) al[rb] = *reinterpret_cast<const V8*>(st + 1 * ARR + lds_off(row, half));
+      o.ah[rb] = *reinterpret_cast<const V8*>(st + 0 * ARR + lds_off(row, half));
+      if (NPROD == 3) o.al[rb] = *reinterpret_cast<const V8*>(st + 1 * ARR + lds_off(row, half));
     }
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) {
       const int row = wc + cb * 32 + j;
-      bh[cb] = *reinterpret_cast<const V8*>(st + IB * ARR + lds_off(row, half));
-      if (NPROD == 3) bl[cb] = *reinterpret_cast<const V8*>(st + 3 * ARR + lds_off(row, half));
+      o.bh[cb] = *reinterpret_cast<const V8*>(st + IB * ARR + lds_off(row, half));
+      if (NPROD == 3) o.bl[cb] = *reinterpret_cast<const V8*>(st + 3 * ARR + lds_off(row, half));
     }
+  };
+  auto mma = [&](const Ops& o) {
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) {
-        acc[rb][cb] = Vec8<T>::mfma(ah[rb], bh[cb], acc[rb][cb]);
+        acc[rb][cb] = Vec8<T>::mfma(o.ah[rb], o.bh[cb], acc[rb][cb]);
         if (NPROD == 3) {
-          acc[rb][cb] = Vec8<T>::mfma(ah[rb], bl[cb], acc[rb][cb]);
-          acc[rb][cb] = Vec8<T>::mfma(al[rb], bh[cb], acc[rb][cb]);
+          acc[rb][cb] = Vec8<T>::mfma(o.ah[rb], o.bl[cb], acc[rb][cb]);
+          acc[rb][cb] = Vec8<T>::mfma(o.al[rb], o.bh[cb], acc[rb][cb]);
         }
       }
+  };
+  // Make stage s readable by every wave: wait for this wave's own loads of
+  // stage s (the `issued - 1 - s` stages issued after it may stay in flight),
+  // then one barrier.  The barrier also means every wave has finished the
+  // MFMAs of stage s-2, whose registers were read from buffer (s-2) % NST =
+  // (s+3) % NST; the load of stage `issued` (= s+3 in the steady state) may
+  // therefore overwrite that buffer right after it.
+  const int nkt = a.Kp / BK;  // a multiple of 4: Kp is a multiple of 64
+  int issued = 0;
+  auto open_stage = [&](int s) {
+    const int later = issued - 1 - s;
+    if (later >= 3) __builtin_amdgcn_s_waitcnt(vmcnt_imm(3 * IPW));
+    else if (later == 2) __builtin_amdgcn_s_waitcnt(vmcnt_imm(2 * IPW));
+    else if (later == 1) __builtin_amdgcn_s_waitcnt(vmcnt_imm(IPW));
+    else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+    asm volatile("s_barrier" ::: "memory");
+    if (issued < nkt) issue(issued++);
+  };
+
+#pragma unroll
+  for (int i = 0; i < AHEAD; ++i) issue(issued++);
+  Ops o0, o1;
+  open_stage(0);
+  lds_read(0, o0);
+  for (int kt = 0; kt < nkt; kt += 2) {
+    open_stage(kt + 1);  // kt + 1 < nkt: nkt is even
+    lds_read(kt + 1, o1);
+    mma(o0);
+    if (kt + 2 < nkt) {
+      open_stage(kt + 2);
+      lds_read(kt + 2, o0);
+    }
+    mma(o1);
   }
   __syncthreads();  // the stage buffers are reused below
 
