@@ -241,8 +241,9 @@ def run_chain_bench(args):
         log("timing the FP64 oracle on the host")
         cpu = cpu_baseline(t128, seed, args.cpu_samples, min(args.cpu_sites, M))
 
+    metric = METRIC if args.workload == "resident" else f"site-samples/s, {args.workload} chain"
     rec = {
-        "metric": METRIC, "value": round(value, 1), "unit": "site-samples/s", "n_gpus": 1,
+        "metric": metric, "value": round(value, 1), "unit": "site-samples/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": FORMS[args.precision]["dtype"],
         "data": "synthetic",
@@ -407,7 +408,7 @@ def run_batch_bench(args):
 WORKLOAD_DEFAULTS = {
     "resident": {"sites": 1024, "chi": 1024, "pool": 16, "chunk": 65536, "precision": "bf16x3", "beside": "fp32"},
     "small": {"sites": 32, "chi": 32, "pool": 1, "chunk": 4096, "precision": "fp32", "beside": ""},
-    "uneven": {"sites": 2048, "chi": 4096, "pool": 2, "chunk": 16384, "precision": "bf16x3", "beside": ""},
+    "uneven": {"sites": 2048, "chi": 4096, "pool": 2, "chunk": 2048, "precision": "bf16x3", "beside": ""},
     "stream": {"sites": 64, "chi": 10000, "pool": 4, "chunk": 65536, "samples": 1 << 17, "precision": "bf16x3",
                "beside": ""},
     "batch": {"chunk": 8192, "samples": 8192, "precision": "fp32", "beside": ""},

@@ -393,7 +393,7 @@ class Sampler:
         return outs
 
     def sample_stored(self, stored, shapes, kind: str, N: int, seed: int, n_offset: int = 0, emit_n: int = 0,
-                      emit_dmax: int = 0, stream=None, raise_numeric: bool = False):
+                      emit_dmax: int = 0, stream=None, raise_numeric: bool = False, displace=None):
         """Sample from site tensors held in a stored form.
 
         stored: list of M uint8 torch tensors (CUDA, or pinned CPU memory), one
@@ -427,6 +427,11 @@ class Sampler:
             opt.emit_dmax = emit_dmax
             opt.emit_probs = emit_probs.data_ptr()
             opt.emit_u = emit_u.data_ptr()
+        if displace is not None:
+            if displace.dtype != torch.complex64 or not displace.is_cuda or tuple(displace.shape) != (N, M) \
+                    or not displace.is_contiguous():
+                raise ValueError("displace must be a contiguous complex64 CUDA tensor of shape (N, M)")
+            opt.displace = displace.data_ptr()
         s = stream if stream is not None else torch.cuda.current_stream(dev)
         opt.stream = s.cuda_stream
         mps_set_options(self.h, opt)

@@ -136,3 +136,24 @@ def test_pageable_host_sites_are_rejected():
         assert "pinned" in mps.mps_last_error()
     finally:
         mps.mps_destroy(h)
+
+
+def test_staged_with_displacement_equals_resident():
+    """Per-sample displacement (Eq. 7) on a staged (pinned-host cf16) chain is
+    bit-identical to the same displacement on the resident expanded chain."""
+    from paper_2512_20064_amd import mps
+    from tests.parity_util import upload
+    print("[gpu-case] staged cf16 host + displacement vs resident", flush=True)
+    ch = _chain(M=8, d=4, chi=32, seed=17)
+    shapes = [t.shape for t in ch]
+    expanded = [_expand_f32(synth.compress_site(t, "cf16"), t.shape, "cf16") for t in ch]
+    N, seed = 700, 3
+    rng = np.random.default_rng(5)
+    mu = (0.3 * (rng.standard_normal((N, len(ch))) + 1j * rng.standard_normal((N, len(ch))))).astype(np.complex64)
+    mu_d = torch.from_numpy(mu).to("cuda")
+    s = mps.Sampler(0, n_chunk=256)
+    ref = s.sample(upload(expanded), N, seed, displace=mu_d)
+    got = s.sample_stored(_stored(ch, "cf16", "host"), shapes, "cf16", N, seed, displace=mu_d)
+    torch.cuda.synchronize()
+    s.close()
+    assert torch.equal(got["outcomes"], ref["outcomes"]) and torch.equal(got["logp"], ref["logp"])
