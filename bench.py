@@ -187,9 +187,22 @@ def run_chain_bench(args):
         del src, dst
         log(f"copy calibration: {args.copy_calibration} MiB device-to-device copy")
 
+    tuned = {}
+
     def run_form(form, steps, warmup):
         sampler = mps.Sampler(0, n_chunk=args.chunk, profile=not args.no_profile, precision=form,
                               graph=args.graph)
+        if args.autotune:
+            # tile order (and chunk, capped at the step size) for this chain and
+            # form; tuning time is outside the timed region
+            t0 = time.perf_counter()
+            rep = sampler.autotune(dev, args.chunk, seed=seed)
+            sampler.opt.n_chunk = args.chunk  # one launch sequence per step, as profiled
+            tuned[form] = {"tile_group": rep["tile_group"], "probe_best_chunk": rep["n_chunk"],
+                           "probe_sites": rep["probe_sites"], "candidates": rep["candidates"],
+                           "gain_vs_default": round(rep["rate"] / rep["default_rate"], 4) if rep["default_rate"] else None,
+                           "seconds": round(time.perf_counter() - t0, 1)}
+            log(f"{form} autotune: {tuned[form]}")
         step = [0]
         # graph capture needs a stream of its own (not the legacy null stream)
         gstream = torch.cuda.Stream() if args.graph else None
@@ -252,6 +265,8 @@ def run_chain_bench(args):
                    "precision": args.precision, "tensor_bytes": distinct_bytes(dev)},
         "roofline": roof, "cpu_baseline": cpu,
     }
+    if tuned:
+        rec["config"]["autotune"] = tuned
     if beside:
         rec["beside"] = beside
         if "fp32" in beside:
@@ -430,6 +445,7 @@ def main():
     ap.add_argument("--storage", default="cf16", choices=["c64", "cf16", "cf8"], help="stream workload storage")
     ap.add_argument("--precision", default=None, choices=sorted(FORMS))
     ap.add_argument("--graph", type=int, default=0, help="replay one captured chunk graph per chunk")
+    ap.add_argument("--autotune", type=int, default=1, help="pick the tile order with mps_autotune first")
     ap.add_argument("--beside", default=None, help="comma-separated forms also timed ('' for none)")
     ap.add_argument("--beside-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -35,14 +35,16 @@ def upload(tensors_c64, device="cuda"):
     return out
 
 
-def compare(tensors_c64, seed, gpu, rows=None, n_offset=0, eps=EPS_FP32, mps_id=0, n_index=None, displace=None):
+def compare(tensors_c64, seed, gpu, rows=None, n_offset=0, eps=EPS_FP32, mps_id=0, n_index=None, displace=None,
+            check_logp=True):
     """Forced-prefix comparison of a GPU result dict with the oracle.
 
     gpu: dict with numpy 'outcomes' [N, M], 'logp' [N], optional 'probs'
     [E, M, dmax] and 'u' [E, M] for the first E rows.  rows: which rows to
     check (default all); n_index: their global sample indices (default
-    n_offset + rows).  Returns a report dict; raises AssertionError on a
-    violated bar.
+    n_offset + rows); check_logp=False skips the logp bar (when only a prefix
+    of the chain's sites is compared).  Returns a report dict; raises
+    AssertionError on a violated bar.
     """
     outc = gpu["outcomes"]
     N, M = outc.shape
@@ -99,6 +101,8 @@ def compare(tensors_c64, seed, gpu, rows=None, n_offset=0, eps=EPS_FP32, mps_id=
     rep["out_of_band_mismatches"] = int((mism & ~band).sum())
     assert rep["out_of_band_mismatches"] == 0, rep
 
+    if not check_logp:  # e.g. a prefix of the chain: the GPU's logp covers every site
+        return rep
     # logp along the GPU path
     p_path = np.take_along_axis(f["probs"], np.maximum(s_gpu, 0)[:, :, None], axis=2)[:, :, 0]
     lp_orc = np.sum(np.log(p_path), axis=1)

@@ -1,0 +1,103 @@
+"""Parity at the measured workloads' full sizes, in the launch configurations
+the benchmark times, on sampled rows that the oracle computes one by one:
+
+* chi = 10^4 window streamed from pinned host memory in complex-fp16
+  (bf16 hi+lo, 2^17 samples in chunks of 65536, sites outer) -- the oracle
+  follows the first 8 sites (ramp 1 .. 4096 and the first 10^4 x 4 x 10^4
+  site), which fixes every conditional probability up to there;
+* uneven chain M = 2048, d_k in {2..6}, chi <= 4096 (bf16 hi+lo, one
+  2048-sample chunk) -- first 10 sites;
+* the batched 256-chain ensemble (FP32, N = 8192 each) -- whole chains, for
+  a few chains and rows.
+"""
+import numpy as np
+import pytest
+
+from paper_2512_20064_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def test_chi10000_streamed_window_prefix_parity():
+    from oracle.sampler import decode_site
+    from paper_2512_20064_amd import mps
+    from tests.parity_util import compare
+    print("[gpu-case] chi=1e4 cf16 pinned window, N=2^17, bf16x3", flush=True)
+    M, chi_max = 20, 10000
+    dl = [4] * M
+    sites, bonds = synth.structured_chain(5, dl, chi_max, pool=4, device="cuda")
+    host, stored = {}, []
+    for A in sites:
+        if id(A) not in host:
+            b = synth.compress_site_torch(A, "cf16")
+            h = torch.empty(b.numel(), dtype=torch.uint8, pin_memory=True)
+            h.copy_(b)
+            host[id(A)] = h
+        stored.append(host[id(A)])
+    shapes = [(bonds[k], 4, bonds[k + 1]) for k in range(M)]
+    del sites
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    N, seed = 1 << 17, 2024
+    s = mps.Sampler(0, n_chunk=65536, precision="bf16x3")
+    r = s.sample_stored(stored, shapes, "cf16", N, seed, emit_n=4)
+    torch.cuda.synchronize()
+    st = s.stats
+    s.close()
+    assert r["status"] == 0 and st.staged_sites == M and st.contract_launches == 2 * M
+    P = 8
+    assert shapes[P - 1] == (chi_max, 4, chi_max)
+    ref = [decode_site(stored[k].numpy(), shapes[k], "cf16") for k in range(P)]
+    gpu = {"outcomes": r["outcomes"][:, :P].cpu().numpy(), "logp": r["logp"].cpu().numpy(),
+           "probs": r["probs"][:, :P].cpu().numpy(), "u": r["u"][:, :P].cpu().numpy()}
+    rows = np.array([0, 1, 2, 3, 65535, 65536, 100000, N - 1])
+    rep = compare(ref, seed, gpu, rows=rows, eps=1e-3, check_logp=False)
+    print(rep, flush=True)
+
+
+def test_uneven_chain_prefix_parity():
+    from paper_2512_20064_amd import mps
+    from tests.parity_util import compare
+    print("[gpu-case] uneven M=2048 chi<=4096, 2048-sample chunk, bf16x3", flush=True)
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([4, 0, 0xD])))
+    dl = [int(x) for x in rng.integers(2, 7, size=2048)]
+    sites, bonds = synth.structured_chain(4, dl, 4096, pool=2, device="cuda")
+    N, seed = 2048, 1003
+    s = mps.Sampler(0, n_chunk=2048, precision="bf16x3")
+    r = s.sample(sites, N, seed, emit_n=8, emit_dmax=6)
+    torch.cuda.synchronize()
+    s.close()
+    assert r["status"] == 0
+    P = 10
+    assert max(bonds[:P + 1]) == 4096
+    ref = [sites[k].cpu().numpy() for k in range(P)]
+    gpu = {"outcomes": r["outcomes"][:, :P].cpu().numpy(), "logp": r["logp"].cpu().numpy(),
+           "probs": r["probs"][:, :P].cpu().numpy(), "u": r["u"][:, :P].cpu().numpy()}
+    rows = np.concatenate([np.arange(8), np.array([1000, N - 1])])
+    rep = compare(ref, seed, gpu, rows=rows, eps=1e-3, check_logp=False)
+    print(rep, flush=True)
+
+
+def test_full_ensemble_sampled_parity():
+    from paper_2512_20064_amd import mps
+    from tests.parity_util import compare, upload
+    print("[gpu-case] 256-chain ensemble, N=8192, fp32", flush=True)
+    specs = synth.ensemble_specs(seed=2, B=256)
+    chains = []
+    for b, (Mb, db, cb) in enumerate(specs):
+        dl = [db] * Mb
+        chains.append(synth.to_c64(synth.random_mps(7, dl, synth.ramp_bonds(dl, cb), mps_id=b, pool=4)))
+    dev = [upload(c) for c in chains]
+    N, seed = 8192, 77
+    s = mps.Sampler(0, n_chunk=8192)
+    outs = s.sample_batch(dev, N, seed)
+    torch.cuda.synchronize()
+    assert s.status == 0
+    s.close()
+    biggest = max(range(256), key=lambda b: specs[b][2] * specs[b][1] * specs[b][0])
+    rows = np.concatenate([np.arange(6), np.array([4096, N - 1])])
+    for b in sorted({0, 128, 255, biggest}):
+        gpu = {"outcomes": outs[b][0].cpu().numpy(), "logp": outs[b][1].cpu().numpy()}
+        rep = compare(chains[b], seed, gpu, rows=rows, mps_id=b)
+        print(b, specs[b], rep, flush=True)
