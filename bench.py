@@ -52,6 +52,8 @@ FORMS = {
                "dtype": "bf16x3"},
     "fp16": {"peak": 2516.6, "mfma_per_alg": 1, "kernel": "contract_lp_kernel<f16,1>", "src": "contract_lp.hip",
              "dtype": "f16"},
+    "fp16x3": {"peak": 2516.6, "mfma_per_alg": 3, "kernel": "contract_lp_kernel<f16,3>", "src": "contract_lp.hip",
+               "dtype": "f16x3"},
 }
 
 

@@ -56,8 +56,12 @@ enum {
   MPS_BF16X3 = 1,    /* split precision: x = hi + lo (bf16 each) for the left
                         vectors and the site tensor; W = Lh*Ah + Lh*Al + Ll*Ah on
                         v_mfma_f32_32x32x16_bf16                                   */
-  MPS_FP16 = 2       /* one fp16 product on v_mfma_f32_32x32x16_f16, left vectors
+  MPS_FP16 = 2,      /* one fp16 product on v_mfma_f32_32x32x16_f16, left vectors
                         renormalised per sample (entries within [-1, 1])           */
+  MPS_FP16X3 = 3     /* split precision in fp16: x = hi + lo (fp16 each), three
+                        products as MPS_BF16X3 on v_mfma_f32_32x32x16_f16; 11-bit
+                        parts (22 bits together) but a narrower exponent range:
+                        lo parts below 2^-24 flush to zero                        */
 };
 
 /* Storage of the site tensors (Section 3.3.2: tensors stored and moved in
@@ -89,7 +93,7 @@ enum {
 typedef struct mps_ctx* mps_handle;
 
 typedef struct {
-  int32_t precision;        /* MPS_FP32, MPS_BF16X3 or MPS_FP16                   */
+  int32_t precision;        /* MPS_FP32, MPS_BF16X3, MPS_FP16 or MPS_FP16X3       */
   int32_t profile;          /* 1: time every kernel launch with HIP events        */
   int64_t n_chunk;          /* samples per pass over the chain; 0 = planner picks */
   int64_t max_device_bytes; /* cap on scratch bytes; 0 = no cap                  */

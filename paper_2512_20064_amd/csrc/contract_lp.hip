@@ -335,14 +335,18 @@ hipError_t launch_contract_t(const ContractLpProb* probs, const int* tn_start, i
 
 hipError_t launch_pack_lp(int form, const PackProb* probs, const int* blk_start, int nprob, int blk_total,
                           hipStream_t s) {
-  return form == kBf16x3 ? launch_pack_t<bf16_t, 3>(probs, blk_start, nprob, blk_total, s)
-                         : launch_pack_t<f16_t, 1>(probs, blk_start, nprob, blk_total, s);
+  if (form == kBf16x3) return launch_pack_t<bf16_t, 3>(probs, blk_start, nprob, blk_total, s);
+  if (form == kFp16x3) return launch_pack_t<f16_t, 3>(probs, blk_start, nprob, blk_total, s);
+  return launch_pack_t<f16_t, 1>(probs, blk_start, nprob, blk_total, s);
 }
 
 hipError_t launch_contract_lp(int form, const ContractLpProb* probs, const int* tn_start, int nprob, int tn_total,
                               const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s) {
-  return form == kBf16x3 ? launch_contract_t<bf16_t, 3>(probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s)
-                         : launch_contract_t<f16_t, 1>(probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s);
+  if (form == kBf16x3)
+    return launch_contract_t<bf16_t, 3>(probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s);
+  if (form == kFp16x3)
+    return launch_contract_t<f16_t, 3>(probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s);
+  return launch_contract_t<f16_t, 1>(probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s);
 }
 
 }  // namespace mps

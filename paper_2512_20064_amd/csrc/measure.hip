@@ -62,7 +62,7 @@ __device__ inline uint64_t philox_word0(uint64_t c0, uint64_t c1, uint64_t k0, u
 
 constexpr int DMAX = 16;
 
-enum Out { kOutF32 = 0, kOutBf16x2 = 1, kOutF16 = 2 };
+enum Out { kOutF32 = 0, kOutBf16x2 = 1, kOutF16 = 2, kOutF16x2 = 3 };
 
 // Left-vector writers for the three operand formats.
 template <int OUT>
@@ -90,19 +90,20 @@ struct LWriter<kOutF32> {
   __device__ void pad_from(int, int) {}
 };
 
-template <>
-struct LWriter<kOutBf16x2> {
+// hi + lo writer for the split forms (T = bf16 or fp16).
+template <typename T>
+struct SplitWriter {
   uint32_t* hi;
   uint32_t* lo;
   size_t row;
   int ld;
-  __device__ LWriter(const MeasureProb& a, int r)
+  __device__ SplitWriter(const MeasureProb& a, int r)
       : hi((uint32_t*)a.Lh), lo((uint32_t*)a.Ll), row((size_t)r), ld(a.ld_out) {}
-  // x = hi + lo with hi = bf16(x) (round to nearest even), lo = bf16(x - hi);
+  // x = hi + lo with hi = T(x) (round to nearest even), lo = T(x - hi);
   // (re, im) of complex r are K elements 2r, 2r+1: one 32-bit word.
   __device__ void put(int r, float x, float y) {
-    const bf16_t xh = (bf16_t)x, yh = (bf16_t)y;
-    const bf16_t xl = (bf16_t)(x - (float)xh), yl = (bf16_t)(y - (float)yh);
+    const T xh = (T)x, yh = (T)y;
+    const T xl = (T)(x - (float)xh), yl = (T)(y - (float)yh);
     const size_t w = kblk_off(row, 2 * r, ld) >> 1;
     hi[w] = pack2(xh, yh);
     lo[w] = pack2(xl, yl);
@@ -113,9 +114,9 @@ struct LWriter<kOutBf16x2> {
     uint32_t h[4], l[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const bf16_t xh = (bf16_t)v[j].x, yh = (bf16_t)v[j].y;
+      const T xh = (T)v[j].x, yh = (T)v[j].y;
       h[j] = pack2(xh, yh);
-      l[j] = pack2((bf16_t)(v[j].x - (float)xh), (bf16_t)(v[j].y - (float)yh));
+      l[j] = pack2((T)(v[j].x - (float)xh), (T)(v[j].y - (float)yh));
     }
     const size_t w = kblk_off(row, 2 * r4, ld) >> 1;
     *reinterpret_cast<uint4*>(hi + w) = make_uint4(h[0], h[1], h[2], h[3]);
@@ -136,9 +137,18 @@ struct LWriter<kOutBf16x2> {
       *reinterpret_cast<uint4*>(lo + w) = make_uint4(0u, 0u, 0u, 0u);
     }
   }
-  static __device__ uint32_t pack2(bf16_t a, bf16_t b) {
+  static __device__ uint32_t pack2(T a, T b) {
     return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
   }
+};
+
+template <>
+struct LWriter<kOutBf16x2> : SplitWriter<bf16_t> {
+  __device__ LWriter(const MeasureProb& a, int r) : SplitWriter<bf16_t>(a, r) {}
+};
+template <>
+struct LWriter<kOutF16x2> : SplitWriter<f16_t> {
+  __device__ LWriter(const MeasureProb& a, int r) : SplitWriter<f16_t>(a, r) {}
 };
 
 template <>
@@ -435,6 +445,8 @@ hipError_t launch_measure(int form, const MeasureProb* probs, int nprob, const C
     launch_measure_t<kOutF32>(displaced, grid, probs, ch, seed, nflag, s);
   else if (form == kBf16x3)
     launch_measure_t<kOutBf16x2>(displaced, grid, probs, ch, seed, nflag, s);
+  else if (form == kFp16x3)
+    launch_measure_t<kOutF16x2>(displaced, grid, probs, ch, seed, nflag, s);
   else
     launch_measure_t<kOutF16>(displaced, grid, probs, ch, seed, nflag, s);
   return hipGetLastError();

@@ -65,7 +65,8 @@ constexpr int64_t kDefaultChunk = 65536;
 constexpr int kDefaultGroup = 4;
 
 int check_options(const mps_options* o) {
-  if (o->precision != MPS_FP32 && o->precision != MPS_BF16X3 && o->precision != MPS_FP16)
+  if (o->precision != MPS_FP32 && o->precision != MPS_BF16X3 && o->precision != MPS_FP16 &&
+      o->precision != MPS_FP16X3)
     return fail(MPS_EINVAL, "unknown precision %d", o->precision);
   if (o->n_chunk < 0) return fail(MPS_EINVAL, "n_chunk < 0");
   if (o->max_device_bytes < 0) return fail(MPS_EINVAL, "max_device_bytes < 0");
@@ -77,7 +78,11 @@ int check_options(const mps_options* o) {
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-int lp_form(int precision) { return precision == MPS_BF16X3 ? mps::kBf16x3 : mps::kFp16; }
+int lp_form(int precision) {
+  return precision == MPS_BF16X3 ? mps::kBf16x3 : precision == MPS_FP16X3 ? mps::kFp16x3 : mps::kFp16;
+}
+// hi + lo operand pairs (three products)
+bool is_split(int precision) { return precision == MPS_BF16X3 || precision == MPS_FP16X3; }
 
 // Largest buffers a chain needs, per sample row (and the packed tensor).
 struct Shape {
@@ -111,14 +116,14 @@ size_t chain_layout(int64_t rows, const Shape& sh, int precision, int64_t nstate
     // whole 256-row tiles: the contraction reads tile rows past the chunk
     const size_t ra = (size_t)((rows + mps::kLpBM - 1) / mps::kLpBM * mps::kLpBM);
     b.Lh = take(ra * sh.kpmax * 2);
-    if (precision == MPS_BF16X3) b.Ll = take(ra * sh.kpmax * 2);
+    if (is_split(precision)) b.Ll = take(ra * sh.kpmax * 2);
   }
   b.logp = take((size_t)rows * sizeof(double));
   b.state = off - start;
   off = start + b.state * (size_t)nstate;
   if (precision != MPS_FP32) {
     b.Bh = take((size_t)sh.bmax * 2);
-    if (precision == MPS_BF16X3) b.Bl = take((size_t)sh.bmax * 2);
+    if (is_split(precision)) b.Bl = take((size_t)sh.bmax * 2);
   }
   b.W = take((size_t)rows * sh.wmax * sizeof(float2));
   b.qpart = take((size_t)rows * sh.qtmax * sizeof(float));
@@ -210,7 +215,7 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
               int kind) {
   const mps_options& o = h->opt;
   const bool lowp = o.precision != MPS_FP32;
-  const bool split = o.precision == MPS_BF16X3;
+  const bool split = is_split(o.precision);
   const int form = lowp ? lp_form(o.precision) : 0;
   const int B = (int)chains.size();
   int Mmax = 0;

@@ -42,7 +42,7 @@ __host__ __device__ inline size_t kblk_off(size_t r, int k, int Kp) {
   return ((r >> 8) * (size_t)(Kp >> 4) + (size_t)(k >> 4)) * 4096 + (r & 255) * 16 + (k & 15);
 }
 
-enum LpForm { kBf16x3 = 1, kFp16 = 2 };
+enum LpForm { kBf16x3 = 1, kFp16 = 2, kFp16x3 = 3 };
 
 // Per-chunk arguments live in device memory (the "current chunk" slot), so
 // that one captured graph of a chunk's launches can be replayed for every
