@@ -262,6 +262,9 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
       const bool on_host = e == hipSuccess && attr.type == hipMemoryTypeHost;
       if (!on_dev && !on_host)
         return fail(MPS_EINVAL, "chain %d site %d: tensor is neither device memory nor pinned host memory", b, k);
+      if (on_dev && attr.device != h->device)
+        return fail(MPS_EINVAL, "chain %d site %d: tensor lives on device %d, the handle runs on device %d", b, k,
+                    attr.device, h->device);
       if (!single) {
         if (!on_dev) return fail(MPS_EINVAL, "chain %d site %d: batched site tensors must be device-resident", b, k);
         continue;
