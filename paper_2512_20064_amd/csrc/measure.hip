@@ -23,9 +23,12 @@
 // does the same job, keeps every element of l' within [-1, 1], and the scale
 // cancels in q_i / S.  The log-norm of the path is tracked in logp.
 //
-// All lanes of the wave evaluate the scalar part (a few dozen FP64
-// operations) redundantly; lane 0 writes the per-sample results and the
-// whole wave gathers the chosen branch.
+// A sample is measured by a group of meas_lanes(chi_r) lanes (the whole wave
+// for chi_r >= 253, down to one lane for chi_r <= 4), so small bonds fill the
+// wave with several samples.  The lanes of a group evaluate the scalar part
+// (a few dozen FP64 operations) redundantly; its first lane writes the
+// per-sample results and the group gathers the chosen branch.  The
+// displaced path always uses the whole wave (it builds D in the wave's LDS).
 
 #include "sweep.h"
 
@@ -86,8 +89,8 @@ struct LWriter<kOutF32> {
         if (r4 + j < n) dst[r4 + j] = v[j];
     }
   }
-  __device__ void pad(const MeasureProb&, int) {}
-  __device__ void pad_from(int, int) {}
+  __device__ void pad(const MeasureProb&, int, int) {}
+  __device__ void pad_from(int, int, int) {}
 };
 
 // hi + lo writer for the split forms (T = bf16 or fp16).
@@ -122,16 +125,17 @@ struct SplitWriter {
     *reinterpret_cast<uint4*>(hi + w) = make_uint4(h[0], h[1], h[2], h[3]);
     *reinterpret_cast<uint4*>(lo + w) = make_uint4(l[0], l[1], l[2], l[3]);
   }
-  __device__ void pad(const MeasureProb& a, int lane) {
-    for (int k = 2 * a.chi_r + 2 * lane; k < ld; k += 128) {
+  // zeros for K in [2 chi_r, ld); lane sl of a group of W lanes
+  __device__ void pad(const MeasureProb& a, int sl, int W) {
+    for (int k = 2 * a.chi_r + 2 * sl; k < ld; k += 2 * W) {
       const size_t w = kblk_off(row, k, ld) >> 1;
       hi[w] = 0u;
       lo[w] = 0u;
     }
   }
   // zeros for K in [k0, ld), k0 a multiple of 8
-  __device__ void pad_from(int k0, int lane) {
-    for (int k = k0 + 8 * lane; k < ld; k += 512) {
+  __device__ void pad_from(int k0, int sl, int W) {
+    for (int k = k0 + 8 * sl; k < ld; k += 8 * W) {
       const size_t w = kblk_off(row, k, ld) >> 1;
       *reinterpret_cast<uint4*>(hi + w) = make_uint4(0u, 0u, 0u, 0u);
       *reinterpret_cast<uint4*>(lo + w) = make_uint4(0u, 0u, 0u, 0u);
@@ -171,11 +175,11 @@ struct LWriter<kOutF16> {
     }
     *reinterpret_cast<uint4*>(hi + (kblk_off(row, 2 * r4, ld) >> 1)) = make_uint4(h[0], h[1], h[2], h[3]);
   }
-  __device__ void pad(const MeasureProb& a, int lane) {
-    for (int k = 2 * a.chi_r + 2 * lane; k < ld; k += 128) hi[kblk_off(row, k, ld) >> 1] = 0u;
+  __device__ void pad(const MeasureProb& a, int sl, int W) {
+    for (int k = 2 * a.chi_r + 2 * sl; k < ld; k += 2 * W) hi[kblk_off(row, k, ld) >> 1] = 0u;
   }
-  __device__ void pad_from(int k0, int lane) {
-    for (int k = k0 + 8 * lane; k < ld; k += 512)
+  __device__ void pad_from(int k0, int sl, int W) {
+    for (int k = k0 + 8 * sl; k < ld; k += 8 * W)
       *reinterpret_cast<uint4*>(hi + (kblk_off(row, k, ld) >> 1)) = make_uint4(0u, 0u, 0u, 0u);
   }
 };
@@ -223,9 +227,11 @@ __global__ __launch_bounds__(256) void measure_kernel(const MeasureProb* probs, 
   const ChunkArgs ch = *chp;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  const int row = blockIdx.x * 4 + wv;
-  if (row >= ch.rows) return;
   const MeasureProb a = probs[blockIdx.y];
+  const int W = DISP ? 64 : meas_lanes(a.chi_r);  // lanes per sample
+  const int sl = lane & (W - 1);                  // lane within the sample's group
+  const int row = (blockIdx.x * 4 + wv) * (64 / W) + lane / W;
+  if (row >= ch.rows) return;
   const int64_t crow = ch.c0 + row;  // row within the call
   double* const logp = a.logp + (a.logp_in_call ? crow : row);
   const int d = a.d, T = a.T;
@@ -310,7 +316,7 @@ __global__ __launch_bounds__(256) void measure_kernel(const MeasureProb* probs, 
   ok = ok && qs > 0.0;
   if (!ok) s = 0;
 
-  if (lane == 0) {
+  if (sl == 0) {
     a.outcomes[(size_t)crow * a.M + a.site] = ok ? s : -1;
     *logp = ok ? lp_prev + (log(qs) - log(S)) : -INFINITY;
     if (alive && !ok) atomicAdd(nflag, 1);
@@ -334,7 +340,7 @@ __global__ __launch_bounds__(256) void measure_kernel(const MeasureProb* probs, 
     const int nq = (a.chi_r + 3) >> 2;
     const bool even = (a.chi_r & 1) == 0;  // src is then 16-byte aligned at every even r
 #pragma unroll 2
-    for (int q4 = lane; q4 < nq; q4 += 64) {
+    for (int q4 = sl; q4 < nq; q4 += W) {
       const int r4 = 4 * q4;
       float2 v[4];
       if (even && r4 + 4 <= a.chi_r) {
@@ -352,7 +358,7 @@ __global__ __launch_bounds__(256) void measure_kernel(const MeasureProb* probs, 
       for (int jj = 0; jj < 4; ++jj) v[jj] = make_float2(v[jj].x * scale, v[jj].y * scale);
       out.put4(r4, v);
     }
-    out.pad_from(8 * nq, lane);
+    out.pad_from(8 * nq, sl, W);
   } else if (ok) {
     // chosen branch of W' = D(mu) W
     const float scale = (float)(1.0 / sqrt(qs));
@@ -367,9 +373,9 @@ __global__ __launch_bounds__(256) void measure_kernel(const MeasureProb* probs, 
       out.put(r, xr * scale, xi * scale);
     }
   } else {
-    for (int r = lane; r < a.chi_r; r += 64) out.put(r, 0.f, 0.f);
+    for (int r = sl; r < a.chi_r; r += W) out.put(r, 0.f, 0.f);
   }
-  out.pad(a, lane);
+  out.pad(a, sl, W);
 }
 
 // chi_0 = 1 (the open left end): every left vector is [1].  FP32: one
@@ -438,9 +444,10 @@ void launch_measure_t(bool displaced, dim3 grid, const MeasureProb* probs, const
 }
 
 hipError_t launch_measure(int form, const MeasureProb* probs, int nprob, const ChunkArgs* ch, int grid_rows,
-                          uint64_t seed, int* nflag, bool displaced, hipStream_t s) {
+                          uint64_t seed, int* nflag, bool displaced, int rows_per_wave, hipStream_t s) {
   if (grid_rows <= 0 || nprob <= 0) return hipSuccess;
-  const dim3 grid((grid_rows + 3) / 4, nprob);
+  const int rpw = displaced ? 1 : (rows_per_wave < 1 ? 1 : rows_per_wave);
+  const dim3 grid((grid_rows + 4 * rpw - 1) / (4 * rpw), nprob);
   if (form == 0)
     launch_measure_t<kOutF32>(displaced, grid, probs, ch, seed, nflag, s);
   else if (form == kBf16x3)

@@ -188,6 +188,7 @@ struct Step {
   int nprob = 0;
   int tn_total = 0;   // contraction column tiles over all problems of the step
   int blk_total = 0;  // packing blocks over all problems of the step
+  int meas_rpw = 64;  // samples per wave in the measurement (set by the largest chi_r)
   size_t contract = 0, tn_start = 0, pack = 0, blk_start = 0, measure = 0;  // offsets in the table blob
   double flops_per_row = 0, meas_bytes_per_row = 0;
 };
@@ -443,6 +444,7 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
         }
         if (single) mp.mu = (const float2*)o.displace;
         ms.push_back(mp);
+        sp.meas_rpw = std::min(sp.meas_rpw, 64 / mps::meas_lanes(chr));
         sp.flops_per_row += 8.0 * (double)K * dk * chr;
         // partial weights read + chosen branch read + new left vector write + outcome + logp read/write
         sp.meas_bytes_per_row += (double)dk * T * 4 + 2.0 * chr * 8 + 4 + 16;
@@ -529,7 +531,7 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
     MPS_TRY(mark(k, 3, stream));
     MPS_TRY(mark(k, 4, stream));
     MPS_HIP(mps::launch_measure(form, (const mps::MeasureProb*)tp(sp.measure), sp.nprob, ch, grid_rows, seed, nflag,
-                                displaced, stream),
+                                displaced, sp.meas_rpw, stream),
             "measurement launch");
     return mark(k, 5, stream);
   };

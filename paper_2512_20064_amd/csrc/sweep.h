@@ -44,6 +44,16 @@ __host__ __device__ inline size_t kblk_off(size_t r, int k, int Kp) {
 
 enum LpForm { kBf16x3 = 1, kFp16 = 2, kFp16x3 = 3 };
 
+// Lanes of a wave that measure one sample: enough to gather the chosen branch
+// (chi_r complex) in pieces of 4, a power of two up to the whole wave.  A
+// wave measures 64 / meas_lanes(chi_r) samples at once.
+__host__ __device__ inline int meas_lanes(int chi_r) {
+  const int nq = (chi_r + 3) >> 2;
+  int w = 1;
+  while (w < nq && w < 64) w <<= 1;
+  return w;
+}
+
 // Per-chunk arguments live in device memory (the "current chunk" slot), so
 // that one captured graph of a chunk's launches can be replayed for every
 // chunk; the launch grids are sized for grid_rows >= rows.
@@ -127,8 +137,9 @@ hipError_t launch_pack_lp(int form, const PackProb* probs, const int* blk_start,
                           hipStream_t s);
 hipError_t launch_contract_lp(int form, const ContractLpProb* probs, const int* tn_start, int nprob, int tn_total,
                               const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s);
-// displaced: the problems carry per-sample displacements (MeasureProb::mu)
+// displaced: the problems carry per-sample displacements (MeasureProb::mu);
+// rows_per_wave: 64 / meas_lanes(largest chi_r of the problems), 1 if displaced.
 hipError_t launch_measure(int form, const MeasureProb* probs, int nprob, const ChunkArgs* ch, int grid_rows,
-                          uint64_t seed, int* nflag, bool displaced, hipStream_t s);
+                          uint64_t seed, int* nflag, bool displaced, int rows_per_wave, hipStream_t s);
 
 }  // namespace mps
