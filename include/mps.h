@@ -240,10 +240,12 @@ typedef struct {
  * largest per-sample work chi[k]*d[k]*chi[k+1] (the plateau shape, which
  * dominates the sweep, together with the ramp that leads to it).  Every pair
  * of n_chunk in {8192, 16384, 32768, 65536, 131072, 262144} (capped at N)
- * and tile_group in {1, 2, 4, 8} is timed as one warm-up and two timed
+ * and tile_group in {1, 2, 4, 8} is timed as one warm-up and three timed
  * single-chunk sweeps over the probe (wall clock around the synchronous
  * call); pairs whose scratch cannot be allocated are skipped.  The pair
- * with the highest site-samples/s wins.  Arguments as in mps_sample, with
+ * with the highest site-samples/s wins if it beats the defaults
+ * (n_chunk = min(N, 65536), tile_group = 4) by at least 2 %; otherwise the
+ * defaults are kept.  Arguments as in mps_sample, with
  * N the job size the handle will be used for (N >= 1); no outcomes are
  * returned.  Debug emits, displacement, profiling and graph replay are off
  * during the probe; the other options are restored afterwards.  The

@@ -63,6 +63,8 @@ constexpr int kMaxChi = 65536;
 constexpr int kMaxChains = 1 << 20;
 constexpr int64_t kDefaultChunk = 65536;
 constexpr int kDefaultGroup = 4;
+constexpr int kTuneReps = 3;          // timed sweeps per autotuner candidate
+constexpr double kTuneMargin = 0.02;  // a candidate must beat the defaults by this much
 
 int check_options(const mps_options* o) {
   if (o->precision != MPS_FP32 && o->precision != MPS_BF16X3 && o->precision != MPS_FP16 &&
@@ -883,14 +885,14 @@ int mps_autotune(mps_handle h, const void* const* tensors, int32_t dtype, const 
         break;
       }
       const auto t0 = std::chrono::steady_clock::now();
-      for (int rep_i = 0; rep_i < 2 && (rr == MPS_OK || rr == MPS_ENUMERIC); ++rep_i)
+      for (int rep_i = 0; rep_i < kTuneReps && (rr == MPS_OK || rr == MPS_ENUMERIC); ++rep_i)
         rr = run_sweep(h, chains, nc, 0, seed, true, dtype);
       const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       if (rr != MPS_OK && rr != MPS_ENUMERIC) {
         err = rr;
         break;
       }
-      const double rate = 2.0 * (double)nc * Mp / dt;
+      const double rate = (double)kTuneReps * nc * Mp / dt;
       r.candidates++;
       if (nc == def_nc && g == kDefaultGroup) r.default_rate = rate;
       if (rate > best) {
@@ -912,6 +914,13 @@ int mps_autotune(mps_handle h, const void* const* tensors, int32_t dtype, const 
   }
   if (err) return err;
   if (best_nc == 0) return fail(MPS_ENOMEM, "autotune: no candidate chunk fits in device memory");
+  // Keep the defaults unless a pair is clearly faster: differences of a few
+  // per cent on a short probe are timing noise.
+  if (r.default_rate > 0 && best < r.default_rate * (1.0 + kTuneMargin)) {
+    best_nc = def_nc;
+    best_g = kDefaultGroup;
+    best = r.default_rate;
+  }
   h->opt.n_chunk = best_nc;
   h->opt.tile_group = best_g;
   r.n_chunk = best_nc;
