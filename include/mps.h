@@ -117,7 +117,11 @@ typedef struct {
    * it for every chunk of the call.  Needs a non-NULL stream; ignored when
    * profile is set or the call has a single chunk.                         */
   int32_t graph;
-  int32_t reserved;
+  /* 0: chains whose bonds stay <= 64 and physical dimensions <= 4 (FP32, sites
+   * device-resident complex64, no displacement) go through all their sites in
+   * one persistent launch per chunk, 32 samples per workgroup, left vectors
+   * and W kept in LDS; 1: every chain takes the per-site launches.          */
+  int32_t fused_small;
   /* Optional per-sample displacement of the physical index (MPS-based GBS
    * simulation, Section 3.4.1): DEVICE complex64 mu[N][M] (row of the call,
    * site), caller-owned, or NULL.  At site k the contraction output of row n
@@ -157,6 +161,9 @@ typedef struct {
   double h2d_ms;              /* summed event time of those copies (profile=1)      */
   double expand_ms;           /* summed event time of the expansion kernels         */
   int64_t staged_sites;       /* sites expanded (and, from host memory, copied)     */
+  int64_t fused_launches;     /* persistent small-bond launches (one per chunk)     */
+  double fused_ms;            /* their summed event time (profile=1)                */
+  double fused_flops;         /* algorithmic contraction flops they performed       */
 } mps_stats;
 
 /* Fill *opt with defaults (FP32, planner chunking, null stream, no emits). */

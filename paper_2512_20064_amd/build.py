@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmps.so")
 ARCH = "gfx950"
 
-SOURCES = ["mps_abi.cpp", "contract_f32.hip", "contract_lp.hip", "measure.hip", "decompress.hip"]
+SOURCES = ["mps_abi.cpp", "contract_f32.hip", "contract_lp.hip", "measure.hip", "decompress.hip", "sweep_small.hip"]
 
 # -packed-fp32-ops off: no v_pk_{add,mul,fma}_f32 in the device code.
 HIP_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",

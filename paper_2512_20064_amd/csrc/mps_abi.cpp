@@ -75,6 +75,7 @@ int check_options(const mps_options* o) {
   if (o->emit_n < 0) return fail(MPS_EINVAL, "emit_n < 0");
   if (o->emit_n > 0 && o->emit_probs && o->emit_dmax < 1) return fail(MPS_EINVAL, "emit_dmax < 1");
   if (o->tile_group < 0) return fail(MPS_EINVAL, "tile_group < 0");
+  if (o->fused_small != 0 && o->fused_small != 1) return fail(MPS_EINVAL, "fused_small must be 0 or 1");
   return MPS_OK;
 }
 
@@ -220,7 +221,7 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
   const bool lowp = o.precision != MPS_FP32;
   const bool split = is_split(o.precision);
   const int form = lowp ? lp_form(o.precision) : 0;
-  const int B = (int)chains.size();
+  int B = (int)chains.size();
   int Mmax = 0;
   for (const Chain& c : chains) Mmax = std::max(Mmax, c.M);
 
@@ -290,6 +291,33 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
   // read once and applied to all samples of the macro batch).
   const bool site_outer = any_staged;
 
+  // ---- chains for the persistent small-bond kernel ----
+  // FP32, device-resident complex64 sites, chi_k <= 64 and d_k <= 4 at every
+  // site, no displacement: the whole chain goes through all its sites in one
+  // launch per chunk (sweep_small.hip).  The other chains take the per-site
+  // launches below.
+  std::vector<Chain> smalls;
+  if (o.precision == MPS_FP32 && o.fused_small == 0 && !any_staged && !(single && o.displace)) {
+    std::vector<Chain> bigs;
+    for (const Chain& c : chains) {
+      int dmax = 0;
+      for (int k = 0; k < c.M; ++k) dmax = std::max(dmax, (int)c.d[k]);
+      (c.sh.chimax <= mps::kSmallChi && dmax <= mps::kSmallD ? smalls : bigs).push_back(c);
+    }
+    chains.swap(bigs);
+    B = (int)chains.size();
+    Mmax = 0;
+    for (const Chain& c : chains) Mmax = std::max(Mmax, c.M);
+  }
+  const int nsmall = (int)smalls.size();
+  size_t small_bytes = 0;
+  double small_flops_per_row = 0.0;
+  for (const Chain& c : smalls) {
+    small_bytes += (size_t)c.M * sizeof(void*) + (size_t)(2 * c.M + 1) * sizeof(int) + 3 * 256;
+    for (int k = 0; k < c.M; ++k) small_flops_per_row += 8.0 * c.chi[k] * c.d[k] * c.chi[k + 1];
+  }
+  if (nsmall) small_bytes += (size_t)nsmall * sizeof(mps::SmallChain) + (size_t)(nsmall + 1) * sizeof(int) + 512;
+
   // ---- plan the chunk ----
   int64_t nc = o.n_chunk > 0 ? o.n_chunk : kDefaultChunk;
   nc = std::min<int64_t>(nc, N);
@@ -302,7 +330,7 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
       t += (size_t)c.M * (sizeof(mps::ContractProb) + sizeof(mps::ContractLpProb) + sizeof(mps::PackProb) +
                           sizeof(mps::MeasureProb) + 2 * sizeof(int));
     t += (size_t)B * sizeof(mps::InitProb) + (size_t)Mmax * 7 * 256 + 4096;
-    return t * (size_t)nstate + (size_t)nstate * sizeof(mps::ChunkArgs) + 512;
+    return t * (size_t)nstate + (size_t)nstate * sizeof(mps::ChunkArgs) + 512 + small_bytes;
   };
   auto scratch_for = [&](int64_t rows, std::vector<ChainBufs>* bufs) -> size_t {
     const int64_t ns = nstate_for(rows);
@@ -468,6 +496,40 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
   for (int64_t c = 0; c < nchunks; ++c)
     cargs[c] = mps::ChunkArgs{(int)std::min<int64_t>(nc, N - c * nc), 0, c * nc, n_offset};
   const size_t chunk_off = site_outer ? tab.put(cargs) : tab.put(std::vector<mps::ChunkArgs>(1));
+  // small-bond chains: site pointers, bonds and dimensions in the tables, 32
+  // samples per workgroup
+  size_t small_off = 0, small_start_off = 0;
+  int small_items = 0;
+  if (nsmall) {
+    const int per = (int)((nc + mps::kSmallRows - 1) / mps::kSmallRows);
+    std::vector<mps::SmallChain> sc(nsmall);
+    std::vector<int> starts(nsmall + 1, 0);
+    for (int i = 0; i < nsmall; ++i) {
+      const Chain& c = smalls[i];
+      const size_t po = tab.put(std::vector<const void*>(c.tensors, c.tensors + c.M));
+      const size_t co = tab.put(std::vector<int>(c.chi, c.chi + c.M + 1));
+      const size_t dof = tab.put(std::vector<int>(c.d, c.d + c.M));
+      mps::SmallChain& q = sc[i];
+      q = mps::SmallChain{};
+      q.A = (const float2* const*)(dtab + po);
+      q.chi = (const int*)(dtab + co);
+      q.d = (const int*)(dtab + dof);
+      q.M = c.M;
+      q.mps_id = c.mps_id;
+      q.outcomes = c.outcomes;
+      q.logp = c.logp;
+      if (single && o.emit_n > 0) {
+        q.emit_n = o.emit_n;
+        q.emit_dmax = o.emit_dmax;
+        q.emit_probs = o.emit_probs;
+        q.emit_u = o.emit_u;
+      }
+      starts[i + 1] = starts[i] + per;
+    }
+    small_items = starts[nsmall];
+    small_off = tab.put(sc);
+    small_start_off = tab.put(starts);
+  }
   if (tab.blob.size() > table_bytes) return fail(MPS_EINVAL, "internal: problem tables exceed their reservation");
   if ((e = hipMemcpyAsync(dtab, tab.blob.data(), tab.blob.size(), hipMemcpyHostToDevice, stream)) != hipSuccess)
     return hip_fail(e, "hipMemcpyAsync (problem tables)");
@@ -480,13 +542,14 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
   // Timing events per site: pack, contraction, measurement, copy, expansion
   // (begin, end); a pair is summed once its end has been recorded and waited.
   constexpr int EV = 10;
-  const size_t nev = prof ? (size_t)EV * Mmax : 0;
+  const size_t nev = prof ? (size_t)EV * Mmax + 2 : 0;  // + the small-bond launch (begin, end)
   while (h->events.size() < nev) {
     hipEvent_t ev;
     if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_fail(e, "hipEventCreate");
     h->events.push_back(ev);
   }
   std::vector<unsigned> rec(prof ? Mmax : 0, 0u);
+  bool rec_small = false;
   auto mark = [&](int k, int which, hipStream_t s) -> int {
     if (!prof) return MPS_OK;
     if (which & 1) rec[k] |= 1u << (which >> 1);
@@ -565,9 +628,21 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
     MPS_HIP(hipEventRecord(h->ev_expand[k & 1], stream), "hipEventRecord");
     return MPS_OK;
   };
+  auto run_small = [&](const mps::ChunkArgs* ch) -> int {
+    if (prof) MPS_HIP(hipEventRecord(h->events[EV * Mmax], stream), "hipEventRecord");
+    MPS_HIP(mps::launch_sweep_small((const mps::SmallChain*)tp(small_off), (const int*)tp(small_start_off), nsmall,
+                                    small_items, ch, seed, nflag, stream),
+            "small-bond sweep launch");
+    if (prof) {
+      MPS_HIP(hipEventRecord(h->events[EV * Mmax + 1], stream), "hipEventRecord");
+      rec_small = true;
+    }
+    return MPS_OK;
+  };
   // All launches of one chunk (chunks-outer order), grids sized for grid_rows.
   auto launch_chunk = [&](int grid_rows) -> int {
     const mps::ChunkArgs* cur = chunk_tab;
+    if (nsmall) MPS_TRY(run_small(cur));
     MPS_TRY(run_init(0, cur, grid_rows));
     for (int k = 0; k < Mmax; ++k) {
       MPS_TRY(run_pack(k));
@@ -602,6 +677,12 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
         *dst[p] += ms;
       }
       rec[k] = 0;
+    }
+    if (rec_small) {
+      float ms = 0.f;
+      MPS_HIP(hipEventElapsedTime(&ms, h->events[EV * Mmax], h->events[EV * Mmax + 1]), "hipEventElapsedTime");
+      st.fused_ms += ms;
+      rec_small = false;
     }
     return MPS_OK;
   };
@@ -667,6 +748,10 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
       }
       if (rc != MPS_OK) break;
       for (int k = 0; k < Mmax; ++k) count(k, ch.rows, true);
+      if (nsmall) {
+        st.fused_launches++;
+        st.fused_flops += small_flops_per_row * ch.rows;
+      }
       rc = accumulate();
     }
     if (use_graph) {

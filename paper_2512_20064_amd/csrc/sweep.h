@@ -118,6 +118,31 @@ struct InitProb {
   int logp_in_call;
 };
 
+// Persistent small-bond sweep (FP32): chains with chi_k <= kSmallChi and
+// d_k <= kSmallD at every site go through all their sites in one launch, 32
+// samples per workgroup (an "item"), left vectors and W kept in LDS.
+constexpr int kSmallRows = 32;
+constexpr int kSmallChi = 64;
+constexpr int kSmallD = 4;
+
+struct SmallChain {
+  const float2* const* A;  // [M] device pointers to the complex64 site tensors
+  const int* chi;          // [M+1]
+  const int* d;            // [M]
+  int M;
+  int emit_dmax;
+  uint64_t mps_id;
+  int32_t* outcomes;       // [N][M] of the call (row c0 + r of chunk row r)
+  double* logp;            // [N] of the call, or NULL
+  int64_t emit_n;          // rows [0, emit_n) of the call emit
+  double* emit_probs;      // [emit_n][M][emit_dmax] or NULL
+  double* emit_u;          // [emit_n][M] or NULL
+};
+// item_start[p] = first item (workgroup) of chain p, nchain + 1 entries;
+// items = item_start[nchain].
+hipError_t launch_sweep_small(const SmallChain* chains, const int* item_start, int nchain, int items,
+                              const ChunkArgs* ch, uint64_t seed, int* nflag, hipStream_t s);
+
 // Stored site tensor (device memory) -> complex64 site tensor.
 struct DecompressProb {
   const void* src;

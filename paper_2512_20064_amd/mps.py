@@ -66,7 +66,7 @@ class mps_options(ctypes.Structure):
         ("emit_probs", ctypes.c_void_p),
         ("emit_u", ctypes.c_void_p),
         ("graph", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("fused_small", ctypes.c_int32),
         ("displace", ctypes.c_void_p),
     ]
 
@@ -101,6 +101,9 @@ class mps_stats(ctypes.Structure):
         ("h2d_ms", ctypes.c_double),
         ("expand_ms", ctypes.c_double),
         ("staged_sites", ctypes.c_int64),
+        ("fused_launches", ctypes.c_int64),
+        ("fused_ms", ctypes.c_double),
+        ("fused_flops", ctypes.c_double),
     ]
 
 
@@ -251,12 +254,13 @@ class Sampler:
 
     def __init__(self, device: int = 0, n_chunk: int = 0, profile: bool = False,
                  max_device_bytes: int = 0, mps_id: int = 0, precision=MPS_FP32, tile_group: int = 0,
-                 graph: bool = False):
+                 graph: bool = False, fused_small: bool = True):
         if isinstance(precision, str):
             precision = PRECISIONS[precision]
         self.opt = mps_options_init()
         self.opt.tile_group = tile_group
         self.opt.graph = int(graph)
+        self.opt.fused_small = 0 if fused_small else 1
         self.opt.n_chunk = n_chunk
         self.opt.profile = int(profile)
         self.opt.max_device_bytes = max_device_bytes

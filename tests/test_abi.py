@@ -39,7 +39,7 @@ def test_exports_every_declared_symbol(lib):
 def test_options_struct_matches_header():
     # the binding's struct must have the header's size (8-byte aligned fields)
     assert ctypes.sizeof(mps.mps_options) == 4 + 4 + 8 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8 + 4 + 4 + 8
-    assert ctypes.sizeof(mps.mps_stats) == 15 * 8
+    assert ctypes.sizeof(mps.mps_stats) == 18 * 8
     assert ctypes.sizeof(mps.mps_tune_report) == 8 + 4 * 4 + 8 + 8
 
 

@@ -27,18 +27,27 @@ def mpsmod():
     return mps
 
 
-FORMS = ["fp32", "bf16x3", "fp16", "fp16x3"]
+# "fp32" lets chains with bonds <= 64 and d <= 4 take the persistent
+# small-bond kernel; "fp32-steps" forces the per-site launches for them.
+FORMS = ["fp32", "fp32-steps", "bf16x3", "fp16", "fp16x3"]
 # Forms held to the stated probability bars (FP32 1e-5, low precision 1e-3).
 # The single-product fp16 form does not meet 1e-3 beyond a few sites; its
 # error is measured against a looser derived bound in test_fp16_error_report.
-PARITY_FORMS = ["fp32", "bf16x3", "fp16x3"]
-EPS = {"fp32": 1e-5, "bf16x3": 1e-3, "fp16": 1e-3, "fp16x3": 1e-3}
+PARITY_FORMS = ["fp32", "fp32-steps", "bf16x3", "fp16x3"]
+EPS = {"fp32": 1e-5, "fp32-steps": 1e-5, "bf16x3": 1e-3, "fp16": 1e-3, "fp16x3": 1e-3}
+
+
+def _sampler(mpsmod, form, **kw):
+    """A Sampler for a test form name ("fp32-steps": FP32 without the
+    persistent small-bond kernel)."""
+    return mpsmod.Sampler(0, precision="fp32" if form == "fp32-steps" else form,
+                          fused_small=form != "fp32-steps", **kw)
 
 
 def _run(mpsmod, tensors_c64, N, seed, n_offset=0, n_chunk=0, emit_n=0, profile=False, precision="fp32"):
     from tests.parity_util import upload
     dev = upload(tensors_c64)
-    s = mpsmod.Sampler(0, n_chunk=n_chunk, profile=profile, precision=precision)
+    s = _sampler(mpsmod, precision, n_chunk=n_chunk, profile=profile)
     r = s.sample(dev, N, seed, n_offset=n_offset, emit_n=emit_n)
     torch.cuda.synchronize()
     out = {"outcomes": r["outcomes"].cpu().numpy(), "logp": r["logp"].cpu().numpy(), "status": r["status"]}
@@ -197,7 +206,8 @@ def test_empty_and_memory_cap(mpsmod):
     r = s.sample(dev, 0, 1)
     assert r["status"] == 0 and r["outcomes"].shape == (0, 6)
     s.close()
-    s = mpsmod.Sampler(0, max_device_bytes=64 * 1024)
+    # the per-site launches keep per-sample scratch, so the cap shrinks their chunk
+    s = mpsmod.Sampler(0, max_device_bytes=64 * 1024, fused_small=False)
     r = s.sample(dev, 1500, 3)
     assert s.stats.n_chunk < 1500
     ref = _run(mpsmod, t, 1500, seed=3)
@@ -230,10 +240,10 @@ def test_graph_replay_matches_eager(mpsmod, form):
     t = _chain(21, 16, 4, 64)
     dev = upload(t)
     st = torch.cuda.Stream()
-    eager = mpsmod.Sampler(0, n_chunk=256, precision=form)
+    eager = _sampler(mpsmod, form, n_chunk=256)
     ref = eager.sample(dev, 1000, 5, n_offset=17, stream=st)
     st.synchronize()
-    g = mpsmod.Sampler(0, n_chunk=256, precision=form, graph=True)
+    g = _sampler(mpsmod, form, n_chunk=256, graph=True)
     for rep in range(3):
         x = torch.randn(4096, device="cuda")  # unrelated eager work between replays
         y = (x * x).sum().item()
@@ -255,7 +265,7 @@ def test_displacement_parity(mpsmod, form):
     t = _chain(31, M, 4, 32)
     rng = np.random.default_rng(5)
     mu = ((rng.standard_normal((N, M)) + 1j * rng.standard_normal((N, M))) * 0.4).astype(np.complex64)
-    s = mpsmod.Sampler(0, precision=form)
+    s = _sampler(mpsmod, form)
     r = s.sample(upload(t), N, 11, emit_n=N, displace=torch.from_numpy(mu).cuda())
     torch.cuda.synchronize()
     g = {k: r[k].cpu().numpy() for k in ("outcomes", "logp", "probs", "u")}
@@ -283,3 +293,29 @@ def test_displaced_vacuum_poisson_on_gpu(mpsmod):
     pois /= pois.sum(axis=2, keepdims=True)
     assert np.max(np.abs(r["probs"].cpu().numpy() - pois)) <= 1e-5
     s.close()
+
+
+def test_small_bond_kernel_runs_and_agrees_with_per_site_launches(mpsmod):
+    """Chains with bonds <= 64 and d <= 4 take one persistent launch per
+    chunk; W is computed exactly as in the per-site FP32 kernel, only the
+    branch-weight sums differ in rounding order, so outcomes agree except for
+    draws within rounding of a CDF boundary and probabilities within 1e-6."""
+    from tests.parity_util import upload
+    _say("persistent small-bond kernel vs per-site launches M=40 d=3 chi=64 N=3000")
+    t = _chain(41, 40, 3, 64)
+    dev = upload(t)
+    a = _sampler(mpsmod, "fp32", n_chunk=1024)
+    ra = a.sample(dev, 3000, 8, emit_n=256)
+    torch.cuda.synchronize()
+    assert a.stats.fused_launches == 3 and a.stats.contract_launches == 0
+    b = _sampler(mpsmod, "fp32-steps", n_chunk=1024)
+    rb = b.sample(dev, 3000, 8, emit_n=256)
+    torch.cuda.synchronize()
+    assert b.stats.fused_launches == 0 and b.stats.contract_launches == 3 * 40
+    agree = (ra["outcomes"] == rb["outcomes"]).all(dim=1)
+    assert agree.float().mean().item() >= 0.99
+    rows = agree[:256]  # emitted rows whose paths agree: same conditionals
+    assert torch.max(torch.abs(ra["probs"][rows] - rb["probs"][rows])).item() <= 1e-6
+    assert torch.equal(ra["u"], rb["u"])
+    a.close()
+    b.close()
