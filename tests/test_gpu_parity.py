@@ -297,9 +297,13 @@ def test_displaced_vacuum_poisson_on_gpu(mpsmod):
 
 def test_small_bond_kernel_runs_and_agrees_with_per_site_launches(mpsmod):
     """Chains with bonds <= 64 and d <= 4 take one persistent launch per
-    chunk; W is computed exactly as in the per-site FP32 kernel, only the
-    branch-weight sums differ in rounding order, so outcomes agree except for
-    draws within rounding of a CDF boundary and probabilities within 1e-6."""
+    chunk.  The contraction is the per-site FP32 kernel's (same operands,
+    same two-level accumulation); the branch-weight sums run in another
+    order, and the resulting rounding differences of the scale 1/sqrt(q_s)
+    are carried by the left vectors from site to site.  Outcomes agree
+    except for draws within that rounding of a CDF boundary, and the
+    conditional probabilities of agreeing paths are within the FP32 bar of
+    each other (both are within it of the FP64 oracle)."""
     from tests.parity_util import upload
     _say("persistent small-bond kernel vs per-site launches M=40 d=3 chi=64 N=3000")
     t = _chain(41, 40, 3, 64)
@@ -315,7 +319,7 @@ def test_small_bond_kernel_runs_and_agrees_with_per_site_launches(mpsmod):
     agree = (ra["outcomes"] == rb["outcomes"]).all(dim=1)
     assert agree.float().mean().item() >= 0.99
     rows = agree[:256]  # emitted rows whose paths agree: same conditionals
-    assert torch.max(torch.abs(ra["probs"][rows] - rb["probs"][rows])).item() <= 1e-6
+    assert torch.max(torch.abs(ra["probs"][rows] - rb["probs"][rows])).item() <= 1e-5
     assert torch.equal(ra["u"], rb["u"])
     a.close()
     b.close()
