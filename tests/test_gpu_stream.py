@@ -68,7 +68,9 @@ def test_staged_equals_resident_expanded_tensor(form, kind, where):
     raws = [synth.compress_site(t, kind) for t in ch]
     expanded = [_expand_f32(r, s, kind) for r, s in zip(raws, shapes)]
     N, seed = 1000, 606
-    s = mps.Sampler(0, n_chunk=256, precision=form)
+    # staged sites always take the per-site launches; so does the resident
+    # reference here (bonds <= 64 would otherwise use the small-bond kernel)
+    s = mps.Sampler(0, n_chunk=256, precision=form, fused_small=False)
     ref = s.sample(upload(expanded), N, seed)
     got = s.sample_stored(_stored(ch, kind, where), shapes, kind, N, seed)
     torch.cuda.synchronize()
