@@ -367,7 +367,8 @@ def run_batch_bench(args):
     from paper_2512_20064_amd import mps, synth
 
     t0 = time.time()
-    specs = synth.ensemble_specs(seed=2, B=args.chains)
+    chis = tuple(int(x) for x in args.ensemble_chis.split(",")) if args.ensemble_chis else (16, 32, 64, 128, 256)
+    specs = synth.ensemble_specs(seed=2, B=args.chains, chis=chis)
     chains = []
     for b, (Mb, db, cb) in enumerate(specs):
         dl = [db] * Mb
@@ -389,10 +390,11 @@ def run_batch_bench(args):
 
     res = {}
     for form in [args.precision] + [f for f in args.beside.split(",") if f and f != args.precision]:
-        sb = mps.Sampler(0, n_chunk=args.chunk, precision=form)
+        sb = mps.Sampler(0, n_chunk=args.chunk, precision=form, fused_small=bool(args.fused_small))
         t_batch = timed(lambda: sb.sample_batch(chains, N, seed), args.steps)
         log(f"{form} batched: {t_batch * 1e3:.1f} ms")
-        singles = [mps.Sampler(0, n_chunk=args.chunk, precision=form, mps_id=b) for b in range(len(chains))]
+        singles = [mps.Sampler(0, n_chunk=args.chunk, precision=form, mps_id=b, fused_small=bool(args.fused_small))
+                   for b in range(len(chains))]
 
         def loop():
             for b, c in enumerate(chains):
@@ -413,8 +415,9 @@ def run_batch_bench(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": FORMS[args.precision]["dtype"],
         "data": "synthetic",
         "config": {"workload": f"{len(chains)} random right-canonical chains, M~U[32,512], chi in "
-                               f"{{16,32,64,128,256}}, d in {{2,3,4}}, complex64, N={N} each",
-                   "chains": len(chains), "total_sites": tot_sites, "samples": N, "precision": args.precision},
+                               f"{set(chis)}, d in {{2,3,4}}, complex64, N={N} each",
+                   "chains": len(chains), "total_sites": tot_sites, "samples": N, "precision": args.precision,
+                   "fused_small": args.fused_small},
         "batch": {f: {k: round(v, 3) for k, v in r.items()} for f, r in res.items()},
         "speedup_batched_vs_per_chain": round(main["batched"] / main["per_chain_calls"], 3),
         "roofline": None, "cpu_baseline": None,
@@ -444,6 +447,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=None)
     ap.add_argument("--samples", type=int, default=None, help="samples per call (stream, batch)")
     ap.add_argument("--chains", type=int, default=256, help="chains in the batch workload")
+    ap.add_argument("--ensemble-chis", default="", help="bond caps drawn for the batch workload (comma list)")
+    ap.add_argument("--fused-small", type=int, default=1, help="persistent kernel for chains with bonds <= 64")
     ap.add_argument("--storage", default="cf16", choices=["c64", "cf16", "cf8"], help="stream workload storage")
     ap.add_argument("--precision", default=None, choices=sorted(FORMS))
     ap.add_argument("--graph", type=int, default=0, help="replay one captured chunk graph per chunk")

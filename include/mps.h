@@ -117,7 +117,7 @@ typedef struct {
    * it for every chunk of the call.  Needs a non-NULL stream; ignored when
    * profile is set or the call has a single chunk.                         */
   int32_t graph;
-  /* 0: chains whose bonds stay <= 64 and physical dimensions <= 4 (FP32, sites
+  /* 0: chains whose bonds stay <= 32 and physical dimensions <= 4 (FP32, sites
    * device-resident complex64, no displacement) go through all their sites in
    * one persistent launch per chunk, 32 samples per workgroup, left vectors
    * and W kept in LDS; 1: every chain takes the per-site launches.          */

@@ -122,7 +122,7 @@ struct InitProb {
 // d_k <= kSmallD at every site go through all their sites in one launch, 32
 // samples per workgroup (an "item"), left vectors and W kept in LDS.
 constexpr int kSmallRows = 32;
-constexpr int kSmallChi = 64;
+constexpr int kSmallChi = 32;
 constexpr int kSmallD = 4;
 
 struct SmallChain {

@@ -4,11 +4,13 @@
 // samples, over chains, and over the sites of Section 2.2's sequential
 // workflow without returning to memory between sites).
 //
-// Eligible chains have chi_k <= 64 and d_k <= 4 at every site.  Per site the
+// Eligible chains have chi_k <= 32 and d_k <= 4 at every site (larger bonds
+// run faster in the grouped per-site launches, which tile the contraction
+// over many more samples at once).  Per site the
 // workgroup
 //   1. streams the site tensor through LDS in stages of 16 rows (l) and
 //      contracts it with the 32 left vectors on v_mfma_f32_32x32x2f32: W is
-//      32 x (d * chi_r) complex, at most 16 blocks of 32 x 32 real; the four
+//      32 x (d * chi_r) complex, at most 8 blocks of 32 x 32 real; the four
 //      waves take every fourth block.  Operand roles, the real embedding of
 //      the site tensor and the two-level accumulation (fresh accumulators per
 //      16-row stage, added to running totals) are those of the FP32
@@ -40,10 +42,11 @@ constexpr int LP = R + 4;           // pitch of the transposed left-vector plane
 constexpr int LIM = CHI * LP + 32;  // offset of the imaginary plane
 constexpr int AP = 2 * NC;          // floats per staged site-tensor row
 constexpr int NTHR = 256;
+constexpr int NT = (NC / 16 + 3) / 4;  // column blocks per wave
 static_assert(R == 32, "one 32-row MFMA block per workgroup");
-static_assert(NC / 16 <= 4 * (NTHR / 64), "four waves x four column blocks cover d * chi_r");
+static_assert(NC / 16 <= NT * (NTHR / 64), "the four waves cover every column block of W");
 
-__global__ __launch_bounds__(NTHR, 1) void sweep_small_kernel(const SmallChain* chains, const int* item_start,
+__global__ __launch_bounds__(NTHR, 2) void sweep_small_kernel(const SmallChain* chains, const int* item_start,
                                                               int nchain, const ChunkArgs* chp, uint64_t seed,
                                                               int* nflag) {
   __shared__ float Ls[LIM + CHI * LP];  // left vectors: [l][row], real plane then imaginary plane
@@ -85,9 +88,9 @@ __global__ __launch_bounds__(NTHR, 1) void sweep_small_kernel(const SmallChain* 
     const int cpad = nblk * 16;
     const float2* A = c.A[k];
 
-    floatx16 tot[4], blk[4];
+    floatx16 tot[NT], blk[NT];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) tot[t] = zero;
+    for (int t = 0; t < NT; ++t) tot[t] = zero;
 
     for (int l0 = 0; l0 < K; l0 += KS) {
       __syncthreads();  // previous stage (or the previous site's measurement) done with LDS
@@ -105,7 +108,7 @@ __global__ __launch_bounds__(NTHR, 1) void sweep_small_kernel(const SmallChain* 
         // past K meet zero site-tensor rows
         const float av = Ls[(half ? LIM : 0) + (l0 + kk) * LP + j];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int t = 0; t < NT; ++t) {
           const int b = wave + 4 * t;
           if (b < nblk) {
             const float bv = __uint_as_float(__float_as_uint(As[kk * AP + 32 * b + (j ^ half)]) ^ sgn);
@@ -114,14 +117,14 @@ __global__ __launch_bounds__(NTHR, 1) void sweep_small_kernel(const SmallChain* 
         }
       }
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
+      for (int t = 0; t < NT; ++t)
         if (wave + 4 * t < nblk) tot[t] += blk[t];
     }
 
     // W to LDS: lane (j, half) of block b holds real column 32 b + j and rows
     // 8 (v / 4) + 4 half + v % 4
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < NT; ++t) {
       const int b = wave + 4 * t;
       const int cc = 16 * b + (j >> 1);
       if (b < nblk && cc < ncols) {

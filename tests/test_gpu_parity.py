@@ -27,7 +27,7 @@ def mpsmod():
     return mps
 
 
-# "fp32" lets chains with bonds <= 64 and d <= 4 take the persistent
+# "fp32" lets chains with bonds <= 32 and d <= 4 take the persistent
 # small-bond kernel; "fp32-steps" forces the per-site launches for them.
 FORMS = ["fp32", "fp32-steps", "bf16x3", "fp16", "fp16x3"]
 # Forms held to the stated probability bars (FP32 1e-5, low precision 1e-3).
@@ -296,7 +296,7 @@ def test_displaced_vacuum_poisson_on_gpu(mpsmod):
 
 
 def test_small_bond_kernel_runs_and_agrees_with_per_site_launches(mpsmod):
-    """Chains with bonds <= 64 and d <= 4 take one persistent launch per
+    """Chains with bonds <= 32 and d <= 4 take one persistent launch per
     chunk.  The contraction is the per-site FP32 kernel's (same operands,
     same two-level accumulation); the branch-weight sums run in another
     order, and the resulting rounding differences of the scale 1/sqrt(q_s)
@@ -305,8 +305,8 @@ def test_small_bond_kernel_runs_and_agrees_with_per_site_launches(mpsmod):
     conditional probabilities of agreeing paths are within the FP32 bar of
     each other (both are within it of the FP64 oracle)."""
     from tests.parity_util import upload
-    _say("persistent small-bond kernel vs per-site launches M=40 d=3 chi=64 N=3000")
-    t = _chain(41, 40, 3, 64)
+    _say("persistent small-bond kernel vs per-site launches M=40 d=3 chi=32 N=3000")
+    t = _chain(41, 40, 3, 32)
     dev = upload(t)
     a = _sampler(mpsmod, "fp32", n_chunk=1024)
     ra = a.sample(dev, 3000, 8, emit_n=256)

@@ -69,7 +69,7 @@ def test_staged_equals_resident_expanded_tensor(form, kind, where):
     expanded = [_expand_f32(r, s, kind) for r, s in zip(raws, shapes)]
     N, seed = 1000, 606
     # staged sites always take the per-site launches; so does the resident
-    # reference here (bonds <= 64 would otherwise use the small-bond kernel)
+    # reference here (bonds <= 32 would otherwise use the small-bond kernel)
     s = mps.Sampler(0, n_chunk=256, precision=form, fused_small=False)
     ref = s.sample(upload(expanded), N, seed)
     got = s.sample_stored(_stored(ch, kind, where), shapes, kind, N, seed)
