@@ -36,7 +36,9 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -215,6 +217,63 @@ struct mps_ctx {
 
 namespace {
 
+// Where a site pointer lives.  A batch can hold tens of thousands of site
+// tensors, most of them in a few allocations: each allocation is asked about
+// once (hipPointerGetAttributes for the memory type, hipMemGetAddressRange for
+// its extent) and later pointers inside a known extent reuse the answer.
+// Only within one call: between calls memory may be freed and reused.
+struct PtrClass {
+  int type = -1;              // hipMemoryTypeDevice / hipMemoryTypeHost, -1 unknown
+  int device = -1;
+  size_t room = SIZE_MAX;     // bytes from the pointer to the end of its allocation (SIZE_MAX if not known)
+};
+class PtrClassifier {
+ public:
+  PtrClass classify(const void* p) {
+    const uintptr_t a = (uintptr_t)p;
+    auto it = ranges_.upper_bound(a);
+    if (it != ranges_.begin()) {
+      --it;
+      if (a < it->second.end) return with_room(it->second, a);
+    }
+    PtrClass pc;
+    hipPointerAttribute_t attr;
+    std::memset(&attr, 0, sizeof attr);
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return pc;
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeHost) return pc;
+    pc.type = attr.type;
+    pc.device = attr.device;
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p);
+    if (e != hipSuccess || size == 0 || a < (uintptr_t)base || a >= (uintptr_t)base + size) {
+      (void)hipGetLastError();
+      return pc;  // extent unknown: this pointer is classified alone
+    }
+    Range r{(uintptr_t)base + size, pc.type, pc.device};
+    ranges_[(uintptr_t)base] = r;
+    return with_room(r, a);
+  }
+
+ private:
+  struct Range {
+    uintptr_t end;
+    int type, device;
+  };
+  static PtrClass with_room(const Range& r, uintptr_t a) {
+    PtrClass pc;
+    pc.type = r.type;
+    pc.device = r.device;
+    pc.room = r.end - a;
+    return pc;
+  }
+  std::map<uintptr_t, Range> ranges_;
+};
+
 int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offset, uint64_t seed, bool single,
               int kind) {
   const mps_options& o = h->opt;
@@ -255,20 +314,22 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
   std::vector<char> host_site(single ? Mmax : 0, 0), staged(single ? Mmax : 0, 0);
   size_t dec_max = 0, comp_max = 0;
   bool any_staged = false;
+  PtrClassifier where;
   for (int b = 0; b < B; ++b) {
     const Chain& c = chains[b];
     for (int k = 0; k < c.M; ++k) {
-      hipPointerAttribute_t attr;
-      std::memset(&attr, 0, sizeof attr);
-      e = hipPointerGetAttributes(&attr, c.tensors[k]);
-      if (e != hipSuccess) (void)hipGetLastError();
-      const bool on_dev = e == hipSuccess && attr.type == hipMemoryTypeDevice;
-      const bool on_host = e == hipSuccess && attr.type == hipMemoryTypeHost;
+      const PtrClass pc = where.classify(c.tensors[k]);
+      const bool on_dev = pc.type == hipMemoryTypeDevice;
+      const bool on_host = pc.type == hipMemoryTypeHost;
       if (!on_dev && !on_host)
         return fail(MPS_EINVAL, "chain %d site %d: tensor is neither device memory nor pinned host memory", b, k);
-      if (on_dev && attr.device != h->device)
+      if (on_dev && pc.device != h->device)
         return fail(MPS_EINVAL, "chain %d site %d: tensor lives on device %d, the handle runs on device %d", b, k,
-                    attr.device, h->device);
+                    pc.device, h->device);
+      const size_t bytes = mps::stored_bytes(single ? kind : MPS_C64, c.chi[k], c.d[k], c.chi[k + 1]);
+      if (pc.room < bytes)
+        return fail(MPS_EINVAL, "chain %d site %d: tensor of %zu B runs past the end of its allocation (%zu B left)",
+                    b, k, bytes, pc.room);
       if (!single) {
         if (!on_dev) return fail(MPS_EINVAL, "chain %d site %d: batched site tensors must be device-resident", b, k);
         continue;

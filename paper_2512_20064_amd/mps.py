@@ -245,6 +245,44 @@ def mps_destroy(h) -> None:
 
 # ---- convenience wrapper over torch device tensors --------------------------
 
+class PreparedBatch:
+    """Descriptors of a list of chains (site pointers, bonds, physical
+    dimensions; chain b has mps_id = b), checked and built once for repeated
+    Sampler.sample_batch calls over the same device-resident tensors.  Holds
+    references to the tensors, so they stay alive while it does."""
+
+    def __init__(self, chains):
+        import torch
+        self.chains = [list(c) for c in chains]
+        self.descs, self._keep = [], []
+        for b, tensors in enumerate(self.chains):
+            shapes = []
+            for k, t in enumerate(tensors):
+                if t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous():
+                    raise ValueError(f"chain {b} site {k}: site tensors must be contiguous complex64 CUDA tensors")
+                shapes.append(tuple(t.shape))
+            chi, d = _bonds_of_shapes(shapes, b)
+            c, keep = make_chain([t.data_ptr() for t in tensors], chi, d, b, 0, None)
+            self.descs.append(c)
+            self._keep.append(keep)
+
+
+def prepare_batch(chains) -> PreparedBatch:
+    return PreparedBatch(chains)
+
+
+def _bonds_of_shapes(shapes, b=0):
+    """chi_0 .. chi_M and d_0 .. d_{M-1} from (chi_k, d_k, chi_{k+1}) shapes."""
+    if not shapes:
+        raise ValueError(f"chain {b}: no sites")
+    for k, sh in enumerate(shapes):
+        if len(sh) != 3:
+            raise ValueError(f"chain {b} site {k}: expected a 3-d tensor (chi_l, d, chi_r)")
+        if k and sh[0] != shapes[k - 1][2]:
+            raise ValueError(f"chain {b} site {k}: left bond {sh[0]} != right bond {shapes[k - 1][2]} of site {k - 1}")
+    return [shapes[0][0]] + [sh[2] for sh in shapes], [sh[1] for sh in shapes]
+
+
 class Sampler:
     """Owns an mps handle; samples from complex64 torch tensors on the GPU.
 
@@ -364,32 +402,28 @@ class Sampler:
 
     def sample_batch(self, chains, N: int, seed: int, n_offset: int = 0, want_logp: bool = True, stream=None,
                      raise_numeric: bool = False):
-        """chains: list of lists of complex64 CUDA tensors; chain b uses mps_id = b.
+        """chains: list of lists of complex64 CUDA tensors, or a PreparedBatch
+        of them (prepare_batch); chain b uses mps_id = b.
 
         Returns a list of (outcomes [N, M_b] int32, logp [N] float64) CUDA tensor pairs.
         """
         import torch
+        prep = chains if isinstance(chains, PreparedBatch) else prepare_batch(chains)
         dev = torch.device("cuda", self.device)
-        outs, keep, descs = [], [], []
-        for b, tensors in enumerate(chains):
-            for t in tensors:
-                if t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous():
-                    raise ValueError("site tensors must be contiguous complex64 CUDA tensors")
-            M = len(tensors)
-            chi = _bonds(tensors)
-            d = [int(t.shape[1]) for t in tensors]
-            o = torch.empty((N, M), dtype=torch.int32, device=dev)
+        outs = []
+        descs = (mps_chain * len(prep.descs))()
+        for b, c in enumerate(prep.descs):
+            o = torch.empty((N, c.M), dtype=torch.int32, device=dev)
             lp = torch.empty((N,), dtype=torch.float64, device=dev) if want_logp else None
-            c, k = make_chain([t.data_ptr() for t in tensors], chi, d, b, o.data_ptr(),
-                              lp.data_ptr() if lp is not None else None)
-            descs.append(c)
-            keep.append(k)
+            descs[b] = c
+            descs[b].outcomes = o.data_ptr() or None
+            descs[b].logp = lp.data_ptr() if lp is not None else None
             outs.append((o, lp))
         opt = mps_options.from_buffer_copy(self.opt)
         s = stream if stream is not None else torch.cuda.current_stream(dev)
         opt.stream = s.cuda_stream
         mps_set_options(self.h, opt)
-        rc = mps_sample_batch(self.h, descs, MPS_C64, N, n_offset, seed)
+        rc = load().mps_sample_batch(self.h, len(prep.descs), descs, MPS_C64, N, n_offset, ctypes.c_uint64(seed))
         self.status = rc
         if rc and (rc != MPS_ENUMERIC or raise_numeric):
             raise MPSError(rc, mps_last_error())

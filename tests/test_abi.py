@@ -169,3 +169,14 @@ def test_autotune_reports_enodev_without_gpu():
         assert rc == mps.MPS_ENODEV
     finally:
         mps.mps_destroy(h)
+
+
+def test_bonds_of_shapes_checks_the_chain():
+    from paper_2512_20064_amd import mps
+    assert mps._bonds_of_shapes([(1, 2, 4), (4, 3, 2), (2, 2, 1)]) == ([1, 4, 2, 1], [2, 3, 2])
+    with pytest.raises(ValueError, match="left bond"):
+        mps._bonds_of_shapes([(1, 2, 4), (3, 2, 1)])
+    with pytest.raises(ValueError, match="3-d"):
+        mps._bonds_of_shapes([(1, 2)])
+    with pytest.raises(ValueError, match="no sites"):
+        mps._bonds_of_shapes([])

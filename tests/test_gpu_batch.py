@@ -35,6 +35,13 @@ def test_batch_equals_single_chain_calls(form):
     big = [c for c in chains if not any(c is x for x in small)]
     assert s.status == 0 and s.stats.contract_launches == (max(len(c) for c in big) if big else 0) * 3  # 3 chunks
     assert s.stats.fused_launches == (3 if small else 0)
+    # descriptors prepared once give the same bits, call after call
+    prep = mps.prepare_batch(dev)
+    for _ in range(2):
+        again = s.sample_batch(prep, N, seed)
+        torch.cuda.synchronize()
+        for (o1, l1), (o2, l2) in zip(outs, again):
+            assert torch.equal(o1, o2) and torch.equal(l1, l2)
     s.close()
     for b, c in enumerate(dev):
         one = mps.Sampler(0, n_chunk=300, precision=form, mps_id=b)

@@ -140,6 +140,33 @@ def test_pageable_host_sites_are_rejected():
         mps.mps_destroy(h)
 
 
+def test_site_past_end_of_allocation_is_rejected():
+    """A site tensor whose shape runs past the end of its device allocation is
+    rejected before anything is launched (the extent comes from
+    hipMemGetAddressRange)."""
+    import ctypes
+    from paper_2512_20064_amd import mps
+    print("[gpu-case] site tensor past the end of its allocation rejected", flush=True)
+    hip = ctypes.CDLL("libamdhip64.so")
+    p = ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(p), ctypes.c_size_t(1 << 16)) == 0
+    h = mps.mps_create(0)
+    try:
+        base, size = ctypes.c_void_p(), ctypes.c_size_t()
+        if hip.hipMemGetAddressRange(ctypes.byref(base), ctypes.byref(size), p) != 0:
+            pytest.skip("hipMemGetAddressRange does not report this allocation")
+        # two sites of 128 B each: (1, 4, 4) and (4, 4, 1); the second starts
+        # 64 B before the end of the allocation
+        sites = [base.value, base.value + size.value - 64]
+        out = torch.empty((8, 2), dtype=torch.int32, device="cuda")
+        rc = mps.mps_sample(h, sites, mps.MPS_C64, [1, 4, 1], [4, 4], 2, 8, 0, 1, out.data_ptr(), 0)
+        assert rc == mps.MPS_EINVAL, (rc, mps.mps_last_error())
+        assert "past the end" in mps.mps_last_error()
+    finally:
+        mps.mps_destroy(h)
+        assert hip.hipFree(p) == 0
+
+
 def test_staged_with_displacement_equals_resident():
     """Per-sample displacement (Eq. 7) on a staged (pinned-host cf16) chain is
     bit-identical to the same displacement on the resident expanded chain."""
