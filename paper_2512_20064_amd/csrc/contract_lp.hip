@@ -140,10 +140,15 @@ __global__ __launch_bounds__(NTHR, 1) void contract_lp_kernel(const ContractLpPr
                                                              int nprob, int tn_total, int tiles_m, int per_xcd,
                                                              int group_m, const ChunkArgs* chp) {
   typedef typename Vec8<T>::type V8;
-  constexpr int NARR = NPROD == 3 ? 4 : 2;  // Ah, [Al], Bh, [Bl]
+  // Products per complex product: 3 = Lh*Bh + Lh*Bl + Ll*Bh (split form);
+  // 2 = Lh*Bh + Ll*Bh (split left vectors, site tensor exact in T, so Bl = 0
+  // and the omitted product adds exact zeros); 1 = Lh*Bh.
+  constexpr int NL = NPROD >= 2 ? 2 : 1;    // left-vector tiles per stage: Ah, [Al]
+  constexpr int NB = NPROD == 3 ? 2 : 1;    // site-tensor tiles per stage: Bh, [Bl]
+  constexpr int NARR = NL + NB;
   constexpr int STAGE = NARR * ARR;
   constexpr int IPW = NARR;                 // 1 KiB load instructions per wave per stage
-  constexpr int IB = NARR / 2;              // index of the Bh tile in a stage
+  constexpr int IB = NL;                    // index of the Bh tile in a stage
   __shared__ __attribute__((aligned(16))) char lds[NST * STAGE];
 
   int tm, tng;
@@ -211,13 +216,13 @@ __global__ __launch_bounds__(NTHR, 1) void contract_lp_kernel(const ContractLpPr
     for (int rb = 0; rb < 2; ++rb) {
       const int row = wr + rb * 32 + j;
       o.ah[rb] = *reinterpret_cast<const V8*>(st + 0 * ARR + lds_off(row, half));
-      if (NPROD == 3) o.al[rb] = *reinterpret_cast<const V8*>(st + 1 * ARR + lds_off(row, half));
+      if (NL == 2) o.al[rb] = *reinterpret_cast<const V8*>(st + 1 * ARR + lds_off(row, half));
     }
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) {
       const int row = wc + cb * 32 + j;
       o.bh[cb] = *reinterpret_cast<const V8*>(st + IB * ARR + lds_off(row, half));
-      if (NPROD == 3) o.bl[cb] = *reinterpret_cast<const V8*>(st + 3 * ARR + lds_off(row, half));
+      if (NB == 2) o.bl[cb] = *reinterpret_cast<const V8*>(st + (IB + 1) * ARR + lds_off(row, half));
     }
   };
   auto mma = [&](const Ops& o) {
@@ -226,10 +231,8 @@ __global__ __launch_bounds__(NTHR, 1) void contract_lp_kernel(const ContractLpPr
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) {
         acc[rb][cb] = Vec8<T>::mfma(o.ah[rb], o.bh[cb], acc[rb][cb]);
-        if (NPROD == 3) {
-          acc[rb][cb] = Vec8<T>::mfma(o.ah[rb], o.bl[cb], acc[rb][cb]);
-          acc[rb][cb] = Vec8<T>::mfma(o.al[rb], o.bh[cb], acc[rb][cb]);
-        }
+        if (NB == 2) acc[rb][cb] = Vec8<T>::mfma(o.ah[rb], o.bl[cb], acc[rb][cb]);
+        if (NL == 2) acc[rb][cb] = Vec8<T>::mfma(o.al[rb], o.bh[cb], acc[rb][cb]);
       }
   };
   // Make stage s readable by every wave: wait for this wave's own loads of
@@ -337,7 +340,7 @@ hipError_t launch_pack_lp(int form, const PackProb* probs, const int* blk_start,
                           hipStream_t s) {
   if (form == kBf16x3) return launch_pack_t<bf16_t, 3>(probs, blk_start, nprob, blk_total, s);
   if (form == kFp16x3) return launch_pack_t<f16_t, 3>(probs, blk_start, nprob, blk_total, s);
-  return launch_pack_t<f16_t, 1>(probs, blk_start, nprob, blk_total, s);
+  return launch_pack_t<f16_t, 1>(probs, blk_start, nprob, blk_total, s);  // kFp16, kFp16x2: high parts only
 }
 
 hipError_t launch_contract_lp(int form, const ContractLpProb* probs, const int* tn_start, int nprob, int tn_total,
@@ -346,6 +349,8 @@ hipError_t launch_contract_lp(int form, const ContractLpProb* probs, const int* 
     return launch_contract_t<bf16_t, 3>(probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s);
   if (form == kFp16x3)
     return launch_contract_t<f16_t, 3>(probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s);
+  if (form == kFp16x2)
+    return launch_contract_t<f16_t, 2>(probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s);
   return launch_contract_t<f16_t, 1>(probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s);
 }
 

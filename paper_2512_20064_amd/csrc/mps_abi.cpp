@@ -636,11 +636,17 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
     MPS_HIP(mps::launch_init(form, (const mps::InitProb*)tp(init_off[s]), B, ch, grid_rows, stream), "init kernel");
     return MPS_OK;
   };
+  // A complex-fp16 stored site holds exact fp16 values: in the fp16 split
+  // form the low parts of its embedding are zero and one of the three
+  // products is skipped (bit-identical result).
+  auto site_form = [&](int k) {
+    return single && form == mps::kFp16x3 && kind == MPS_CF16 && staged[k] ? (int)mps::kFp16x2 : form;
+  };
   auto run_pack = [&](int k) -> int {
     if (!lowp) return MPS_OK;
     const Step& sp = steps[k];
     MPS_TRY(mark(k, 0, stream));
-    MPS_HIP(mps::launch_pack_lp(form, (const mps::PackProb*)tp(sp.pack), (const int*)tp(sp.blk_start), sp.nprob,
+    MPS_HIP(mps::launch_pack_lp(site_form(k), (const mps::PackProb*)tp(sp.pack), (const int*)tp(sp.blk_start), sp.nprob,
                                 sp.blk_total, stream),
             "pack launch");
     return mark(k, 1, stream);
@@ -649,7 +655,7 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
     const Step& sp = steps[(size_t)s * Mmax + k];
     MPS_TRY(mark(k, 2, stream));
     if (lowp)
-      e = mps::launch_contract_lp(form, (const mps::ContractLpProb*)tp(sp.contract), (const int*)tp(sp.tn_start),
+      e = mps::launch_contract_lp(site_form(k), (const mps::ContractLpProb*)tp(sp.contract), (const int*)tp(sp.tn_start),
                                   sp.nprob, sp.tn_total, ch, grid_rows, group, stream);
     else
       e = mps::launch_contract_f32((const mps::ContractProb*)tp(sp.contract), (const int*)tp(sp.tn_start), sp.nprob,

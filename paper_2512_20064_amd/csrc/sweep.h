@@ -42,7 +42,12 @@ __host__ __device__ inline size_t kblk_off(size_t r, int k, int Kp) {
   return ((r >> 8) * (size_t)(Kp >> 4) + (size_t)(k >> 4)) * 4096 + (r & 255) * 16 + (k & 15);
 }
 
-enum LpForm { kBf16x3 = 1, kFp16 = 2, kFp16x3 = 3 };
+// kFp16x2 is kFp16x3 for a site tensor whose entries are exact fp16 values
+// (a complex-fp16 stored site): the low parts of its embedding are zero, so
+// the product with them is skipped, and the result is bit-identical to
+// kFp16x3 on the same tensor.  Packing and contraction only; the left
+// vectors are those of kFp16x3.
+enum LpForm { kBf16x3 = 1, kFp16 = 2, kFp16x3 = 3, kFp16x2 = 4 };
 
 // Lanes of a wave that measure one sample: enough to gather the chosen branch
 // (chi_r complex) in pieces of 4, a power of two up to the whole wave.  A

@@ -24,7 +24,8 @@ import numpy as np
 import oracle
 from paper_2512_20064_amd import synth
 
-EPS_FP32 = 1e-5
+EPS_FP32 = 1e-5  # conditional-probability bar, FP32 contraction
+EPS_LOWP = 1e-3  # conditional-probability bar, 16-bit split forms
 
 
 def upload(tensors_c64, device="cuda"):

@@ -54,7 +54,7 @@ def _stored(tensors, kind, where):
 CASES = [("c64", "host"), ("cf16", "device"), ("cf16", "host"), ("cf8", "device"), ("cf8", "mixed")]
 
 
-@pytest.mark.parametrize("form", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("form", ["fp32", "bf16x3", "fp16x3"])
 @pytest.mark.parametrize("kind,where", CASES)
 def test_staged_equals_resident_expanded_tensor(form, kind, where):
     """A staged call is bit-identical to a device-resident complex64 call on
@@ -87,24 +87,27 @@ def test_staged_equals_resident_expanded_tensor(form, kind, where):
     assert st.h2d_bytes == nb_host
 
 
-@pytest.mark.parametrize("kind", ["cf16", "cf8"])
-def test_staged_parity_with_oracle(kind):
+@pytest.mark.parametrize("kind,form", [("cf16", "fp32"), ("cf8", "fp32"), ("cf16", "fp16x3"), ("cf8", "fp16x3")])
+def test_staged_parity_with_oracle(kind, form):
     """Compressed pinned-host sites against the FP64 oracle run on the same
-    (expanded) tensor values, forced-prefix protocol, FP32 bars."""
+    (expanded) tensor values, forced-prefix protocol, the form's bars.  With
+    complex-fp16 sites the fp16 split form runs two products per complex
+    product (the site tensor's low parts are zero)."""
     from paper_2512_20064_amd import mps
-    from tests.parity_util import compare
-    print(f"[gpu-case] staged {kind} host parity vs oracle", flush=True)
+    from tests.parity_util import compare, EPS_LOWP
+    print(f"[gpu-case] staged {kind} host parity vs oracle {form}", flush=True)
     ch = _chain(M=14, d=4, chi=64, seed=7)
     shapes = [t.shape for t in ch]
     expanded = [_expand_f32(synth.compress_site(t, kind), t.shape, kind) for t in ch]
     N, seed = 1536, 99
-    s = mps.Sampler(0, n_chunk=512)
+    s = mps.Sampler(0, n_chunk=512, precision=form)
     r = s.sample_stored(_stored(ch, kind, "host"), shapes, kind, N, seed, emit_n=256)
     torch.cuda.synchronize()
     s.close()
     gpu = {k: v.cpu().numpy() for k, v in r.items() if k != "status"}
     rows = np.concatenate([np.arange(256), np.arange(N - 200, N)])
-    rep = compare(expanded, seed, gpu, rows=rows)
+    kw = {} if form == "fp32" else {"eps": EPS_LOWP}
+    rep = compare(expanded, seed, gpu, rows=rows, **kw)
     print(rep, flush=True)
 
 
