@@ -126,14 +126,15 @@ static_assert(BM == 256 && BN == 256 && BK == 16, "layout below assumes 256 x 25
 __device__ inline int swz(int row) { return ((row >> 2) ^ (row >> 3)) & 1; }
 __device__ inline int lds_off(int row, int chunk) { return row * 32 + ((chunk ^ swz(row)) << 4); }
 
-// s_waitcnt immediate waiting for at most n outstanding vector-memory
-// operations (n < 16) and nothing else.
-constexpr unsigned vmcnt_imm(unsigned n) { return (n & 0xF) | (0x7u << 4) | (0xFu << 8); }
+// s_waitcnt immediate: at most n vector-memory operations of this wave still
+// outstanding, and every LDS read of this wave returned (lgkmcnt 0); expcnt
+// is not waited on.
+constexpr unsigned vmcnt_lgkm0_imm(unsigned n) { return (n & 0xF) | (0x7u << 4); }
 
 // Pipeline: stage kt lives in LDS buffer kt % NST.  Operand tiles go straight
 // from memory into LDS (global_load_lds_dwordx4: no staging registers and no
-// LDS store phase), two to three stages ahead of the stage being read from
-// LDS, which is itself one stage ahead of the MFMAs (see open_stage below).
+// LDS store phase), four stages ahead of the stage being read from LDS,
+// which is itself one stage ahead of the MFMAs (see open_stage below).
 // One stage of MFMAs is ~1500 cycles per SIMD.
 template <typename T, int NPROD>
 __global__ __launch_bounds__(NTHR, 1) void contract_lp_kernel(const ContractLpProb* probs, const int* tn_start,
@@ -236,19 +237,21 @@ __global__ __launch_bounds__(NTHR, 1) void contract_lp_kernel(const ContractLpPr
       }
   };
   // Make stage s readable by every wave: wait for this wave's own loads of
-  // stage s (the `issued - 1 - s` stages issued after it may stay in flight),
-  // then one barrier.  The barrier also means every wave has finished the
-  // MFMAs of stage s-2, whose registers were read from buffer (s-2) % NST =
-  // (s+3) % NST; the load of stage `issued` (= s+3 in the steady state) may
-  // therefore overwrite that buffer right after it.
+  // stage s (the `issued - 1 - s` stages issued after it may stay in flight)
+  // and for this wave's LDS reads, then one barrier.  In the steady state
+  // `issued` = s + 4 on entry, so the load issued after the barrier (stage
+  // s + 4) goes into buffer (s + 4) % NST = (s - 1) % NST, the buffer of
+  // stage s - 1, whose LDS reads every wave issued in the previous step: the
+  // LDS-read wait before the barrier is what makes that overwrite safe.  It
+  // costs nothing (those reads were issued a whole stage of MFMAs earlier).
   const int nkt = a.Kp / BK;  // a multiple of 4: Kp is a multiple of 64
   int issued = 0;
   auto open_stage = [&](int s) {
     const int later = issued - 1 - s;
-    if (later >= 3) __builtin_amdgcn_s_waitcnt(vmcnt_imm(3 * IPW));
-    else if (later == 2) __builtin_amdgcn_s_waitcnt(vmcnt_imm(2 * IPW));
-    else if (later == 1) __builtin_amdgcn_s_waitcnt(vmcnt_imm(IPW));
-    else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+    if (later >= 3) __builtin_amdgcn_s_waitcnt(vmcnt_lgkm0_imm(3 * IPW));
+    else if (later == 2) __builtin_amdgcn_s_waitcnt(vmcnt_lgkm0_imm(2 * IPW));
+    else if (later == 1) __builtin_amdgcn_s_waitcnt(vmcnt_lgkm0_imm(IPW));
+    else __builtin_amdgcn_s_waitcnt(vmcnt_lgkm0_imm(0));
     asm volatile("s_barrier" ::: "memory");
     if (issued < nkt) issue(issued++);
   };
