@@ -117,10 +117,13 @@ typedef struct {
    * it for every chunk of the call.  Needs a non-NULL stream; ignored when
    * profile is set or the call has a single chunk.                         */
   int32_t graph;
-  /* 0: chains whose bonds stay <= 32 and physical dimensions <= 4 (FP32, sites
+  /* 0: chains whose bonds stay <= 32 and physical dimensions <= 4 (sites
    * device-resident complex64, no displacement) go through all their sites in
    * one persistent launch per chunk, 32 samples per workgroup, left vectors
-   * and W kept in LDS; 1: every chain takes the per-site launches.          */
+   * and W kept in LDS, with the FP32 contraction whatever the precision form
+   * (at these bonds it is faster than the 16-bit forms and at least as
+   * accurate); 1: every chain takes the per-site launches of the handle's
+   * precision form.                                                        */
   int32_t fused_small;
   /* Optional per-sample displacement of the physical index (MPS-based GBS
    * simulation, Section 3.4.1): DEVICE complex64 mu[N][M] (row of the call,

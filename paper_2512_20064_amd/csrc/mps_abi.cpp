@@ -353,13 +353,15 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
   const bool site_outer = any_staged;
 
   // ---- chains for the persistent small-bond kernel ----
-  // FP32, device-resident complex64 sites, chi_k <= 32 and d_k <= 4 at every
-  // site, no displacement: the whole chain goes through all its sites in one
-  // launch per chunk (sweep_small.hip).  The other chains take the per-site
+  // Device-resident complex64 sites, chi_k <= 32 and d_k <= 4 at every site,
+  // no displacement: the whole chain goes through all its sites in one
+  // launch per chunk (sweep_small.hip), with the FP32 contraction in every
+  // precision form (at these bonds it is faster than the per-site 16-bit
+  // launches, and at least as accurate).  The other chains take the per-site
   // launches below.  The choice depends on the chain alone, so a chain gives
   // the same bits in a batch as in a call of its own.
   std::vector<Chain> smalls;
-  if (o.precision == MPS_FP32 && o.fused_small == 0 && !any_staged && !(single && o.displace)) {
+  if (o.fused_small == 0 && !any_staged && !(single && o.displace)) {
     std::vector<Chain> bigs;
     for (const Chain& c : chains) {
       int dmax = 0;

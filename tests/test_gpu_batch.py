@@ -30,8 +30,8 @@ def test_batch_equals_single_chain_calls(form):
     s = mps.Sampler(0, n_chunk=300, precision=form)
     outs = s.sample_batch(dev, N, seed)
     torch.cuda.synchronize()
-    # chains with bonds <= 32 (d <= 4 here) take the persistent kernel in FP32
-    small = [c for c in chains if form == "fp32" and max(max(t.shape[0], t.shape[2]) for t in c) <= 32]
+    # chains with bonds <= 32 (d <= 4 here) take the persistent FP32 kernel
+    small = [c for c in chains if max(max(t.shape[0], t.shape[2]) for t in c) <= 32]
     big = [c for c in chains if not any(c is x for x in small)]
     assert s.status == 0 and s.stats.contract_launches == (max(len(c) for c in big) if big else 0) * 3  # 3 chunks
     assert s.stats.fused_launches == (3 if small else 0)

@@ -28,7 +28,9 @@ def mpsmod():
 
 
 # "fp32" lets chains with bonds <= 32 and d <= 4 take the persistent
-# small-bond kernel; "fp32-steps" forces the per-site launches for them.
+# small-bond kernel (FP32 in every form); "fp32-steps" and the 16-bit forms
+# here force the per-site launches, so that the 16-bit kernels are the ones
+# tested on small chains too.
 FORMS = ["fp32", "fp32-steps", "bf16x3", "fp16", "fp16x3"]
 # Forms held to the stated probability bars (FP32 1e-5, low precision 1e-3).
 # The single-product fp16 form does not meet 1e-3 beyond a few sites; its
@@ -39,9 +41,9 @@ EPS = {"fp32": 1e-5, "fp32-steps": 1e-5, "bf16x3": 1e-3, "fp16": 1e-3, "fp16x3":
 
 def _sampler(mpsmod, form, **kw):
     """A Sampler for a test form name ("fp32-steps": FP32 without the
-    persistent small-bond kernel)."""
+    persistent small-bond kernel; the 16-bit forms also without it)."""
     return mpsmod.Sampler(0, precision="fp32" if form == "fp32-steps" else form,
-                          fused_small=form != "fp32-steps", **kw)
+                          fused_small=form == "fp32", **kw)
 
 
 def _run(mpsmod, tensors_c64, N, seed, n_offset=0, n_chunk=0, emit_n=0, profile=False, precision="fp32"):
@@ -321,5 +323,13 @@ def test_small_bond_kernel_runs_and_agrees_with_per_site_launches(mpsmod):
     rows = agree[:256]  # emitted rows whose paths agree: same conditionals
     assert torch.max(torch.abs(ra["probs"][rows] - rb["probs"][rows])).item() <= 1e-5
     assert torch.equal(ra["u"], rb["u"])
+    # a 16-bit handle sends the same chain through the same FP32 kernel
+    c = mpsmod.Sampler(0, precision="bf16x3", n_chunk=1024)
+    rc = c.sample(dev, 3000, 8, emit_n=256)
+    torch.cuda.synchronize()
+    assert c.stats.fused_launches == 3 and c.stats.contract_launches == 0 and c.stats.pack_launches == 0
+    for key in ("outcomes", "logp", "probs", "u"):
+        assert torch.equal(rc[key], ra[key]), key
     a.close()
     b.close()
+    c.close()
