@@ -2,11 +2,12 @@
 the benchmark times, on sampled rows that the oracle computes one by one:
 
 * chi = 10^4 window streamed from pinned host memory in complex-fp16
-  (bf16 hi+lo, 2^17 samples in chunks of 65536, sites outer) -- the oracle
+  (fp16 hi+lo, two products, and bf16 hi+lo; 2^17 samples in chunks of
+  65536, sites outer) -- the oracle
   follows the first 8 sites (ramp 1 .. 4096 and the first 10^4 x 4 x 10^4
   site), which fixes every conditional probability up to there;
 * uneven chain M = 2048, d_k in {2..6}, chi <= 4096 (bf16 hi+lo, one
-  2048-sample chunk) -- first 10 sites;
+  8192-sample chunk) -- first 10 sites;
 * the batched 256-chain ensemble (FP32, N = 8192 each) -- whole chains, for
   a few chains and rows.
 """
@@ -19,11 +20,14 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def test_chi10000_streamed_window_prefix_parity():
+@pytest.mark.parametrize("form", ["fp16x3", "bf16x3"])
+def test_chi10000_streamed_window_prefix_parity(form):
+    """fp16x3 runs two MFMA products per complex product on these fp16-exact
+    sites (the streamed workload's default); bf16x3 runs three."""
     from oracle.sampler import decode_site
     from paper_2512_20064_amd import mps
     from tests.parity_util import compare
-    print("[gpu-case] chi=1e4 cf16 pinned window, N=2^17, bf16x3", flush=True)
+    print(f"[gpu-case] chi=1e4 cf16 pinned window, N=2^17, {form}", flush=True)
     M, chi_max = 20, 10000
     dl = [4] * M
     sites, bonds = synth.structured_chain(5, dl, chi_max, pool=4, device="cuda")
@@ -40,7 +44,7 @@ def test_chi10000_streamed_window_prefix_parity():
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     N, seed = 1 << 17, 2024
-    s = mps.Sampler(0, n_chunk=65536, precision="bf16x3")
+    s = mps.Sampler(0, n_chunk=65536, precision=form)
     r = s.sample_stored(stored, shapes, "cf16", N, seed, emit_n=4)
     torch.cuda.synchronize()
     st = s.stats
@@ -59,12 +63,12 @@ def test_chi10000_streamed_window_prefix_parity():
 def test_uneven_chain_prefix_parity():
     from paper_2512_20064_amd import mps
     from tests.parity_util import compare
-    print("[gpu-case] uneven M=2048 chi<=4096, 2048-sample chunk, bf16x3", flush=True)
+    print("[gpu-case] uneven M=2048 chi<=4096, 8192-sample chunk, bf16x3", flush=True)
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([4, 0, 0xD])))
     dl = [int(x) for x in rng.integers(2, 7, size=2048)]
     sites, bonds = synth.structured_chain(4, dl, 4096, pool=2, device="cuda")
-    N, seed = 2048, 1003
-    s = mps.Sampler(0, n_chunk=2048, precision="bf16x3")
+    N, seed = 8192, 1003
+    s = mps.Sampler(0, n_chunk=8192, precision="bf16x3")
     r = s.sample(sites, N, seed, emit_n=8, emit_dmax=6)
     torch.cuda.synchronize()
     s.close()
@@ -74,7 +78,7 @@ def test_uneven_chain_prefix_parity():
     ref = [sites[k].cpu().numpy() for k in range(P)]
     gpu = {"outcomes": r["outcomes"][:, :P].cpu().numpy(), "logp": r["logp"].cpu().numpy(),
            "probs": r["probs"][:, :P].cpu().numpy(), "u": r["u"][:, :P].cpu().numpy()}
-    rows = np.concatenate([np.arange(8), np.array([1000, N - 1])])
+    rows = np.concatenate([np.arange(8), np.array([1000, 4095, 4096, N - 1])])
     rep = compare(ref, seed, gpu, rows=rows, eps=1e-3, check_logp=False)
     print(rep, flush=True)
 
