@@ -170,6 +170,18 @@ def roofline_of(form, c_fl, c_n, c_ms, dt, m_ms, p_ms, chunk, products=None):
     }
 
 
+def roofline_small(f_fl, f_n, f_ms, dt):
+    """Roofline of the persistent small-bond kernel (the whole sweep of chains
+    with bonds <= 32 in one launch per chunk): algorithmic flops of its FP32
+    contractions over the event-timed launch, against the FP32 MFMA peak.
+    The kernel is latency-bound at these sizes, so the fraction is low."""
+    alg = (f_fl / f_n) / (f_ms / f_n * 1e-3) / 1e12
+    return {"bound": "mfma", "achieved": round(alg, 3), "peak": 157.3, "unit": "TFLOP/s",
+            "frac": round(alg / 157.3, 5), "traffic": None, "kernel": "sweep_small_kernel",
+            "alg_flops_per_launch": round(f_fl / f_n), "avg_launch_ms": round(f_ms / f_n, 4), "launches": f_n,
+            "time_share": {"sweep_small": round(f_ms * 1e-3 / dt, 4)}}
+
+
 def check_one_gpu(args):
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -230,8 +242,8 @@ def run_chain_bench(args):
             torch.cuda.synchronize()
             log(f"{form} warmup step {w} done")
         torch.cuda.synchronize()
-        c_ms = m_ms = p_ms = c_fl = 0.0
-        c_n = 0
+        c_ms = m_ms = p_ms = c_fl = f_ms = f_fl = 0.0
+        c_n = f_n = 0
         t0 = time.perf_counter()
         for s_ in range(steps):
             one_step()
@@ -241,14 +253,19 @@ def run_chain_bench(args):
             p_ms += st.pack_ms
             c_fl += st.contract_flops
             c_n += st.contract_launches
+            f_ms += st.fused_ms
+            f_fl += st.fused_flops
+            f_n += st.fused_launches
             log(f"{form} timed step {s_} done")
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         sampler.close()
         out = {"value": args.chunk * M * steps / dt, "ms_per_step": dt / steps * 1e3, "dt": dt,
-               "alg_tflops": c_fl / dt / 1e12}
+               "alg_tflops": (c_fl + f_fl) / dt / 1e12}
         if not args.no_profile and c_ms > 0:
             out["roofline"] = roofline_of(form, c_fl, c_n, c_ms, dt, m_ms, p_ms, args.chunk)
+        elif not args.no_profile and f_ms > 0:
+            out["roofline"] = roofline_small(f_fl, f_n, f_ms, dt)
         return out
 
     main_res = run_form(args.precision, args.steps, args.warmup)

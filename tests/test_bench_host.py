@@ -50,3 +50,10 @@ def test_more_than_one_gpu_is_refused():
     assert p.returncode == 2
     msg = json.loads(p.stdout.strip().splitlines()[-1])
     assert "one GPU" in msg["error"]
+
+
+def test_small_bond_roofline():
+    r = bench.roofline_small(3e12, 3, 300.0, 1.0)  # 1e12 flops per 100 ms launch
+    assert r["achieved"] == pytest.approx(10.0) and r["peak"] == 157.3
+    assert r["kernel"] == "sweep_small_kernel" and r["avg_launch_ms"] == pytest.approx(100.0)
+    assert r["time_share"]["sweep_small"] == pytest.approx(0.3)
