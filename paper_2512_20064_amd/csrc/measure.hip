@@ -1,5 +1,5 @@
 // Measurement step of the MPS sampling sweep (Section 3.3.1, Algorithm 1),
-// for gfx950.  One wave per sample:
+// for gfx950.  Per sample:
 //
 //   q_i   = sum over the column tiles of the contraction's partial weights,
 //           added in FP64 in a fixed order;
@@ -23,12 +23,12 @@
 // does the same job, keeps every element of l' within [-1, 1], and the scale
 // cancels in q_i / S.  The log-norm of the path is tracked in logp.
 //
-// A sample is measured by a group of meas_lanes(chi_r) lanes (the whole wave
-// for chi_r >= 253, down to one lane for chi_r <= 4), so small bonds fill the
-// wave with several samples.  The lanes of a group evaluate the scalar part
-// (a few dozen FP64 operations) redundantly; its first lane writes the
-// per-sample results and the group gathers the chosen branch.  The
-// displaced path always uses the whole wave (it builds D in the wave's LDS).
+// Without displacement (measure_rows_kernel) a workgroup measures 64 rows:
+// one lane per row makes the decision (the scalar FP64 and 64-bit integer
+// work, once per row), then groups of meas_lanes(chi_r) lanes (the whole wave
+// for chi_r >= 253, down to one lane for chi_r <= 4) gather the chosen
+// branches.  With displacement (measure_kernel) one wave measures one row:
+// it builds that row's D in its LDS and forms the weights from W' directly.
 
 #include "philox.h"
 #include "sweep.h"
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(256) void measure_kernel(const MeasureProb* probs, 
         for (int jj = 0; jj < 4; ++jj) v[jj] = r4 + jj < a.chi_r ? src[r4 + jj] : make_float2(0.f, 0.f);
       }
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) v[jj] = make_float2(v[jj].x * scale, v[jj].y * scale);
+      for (int jj = 0; jj < 4; ++jj) v[jj] = make_float2(__fmul_rn(v[jj].x, scale), __fmul_rn(v[jj].y, scale));
       out.put4(r4, v);
     }
     out.pad_from(8 * nq, sl, W);
@@ -347,12 +347,151 @@ __global__ __launch_bounds__(256) void measure_kernel(const MeasureProb* probs, 
         xr += g.x * w.x - g.y * w.y;
         xi += g.x * w.y + g.y * w.x;
       }
-      out.put(r, xr * scale, xi * scale);
+      out.put(r, __fmul_rn(xr, scale), __fmul_rn(xi, scale));
     }
   } else {
     for (int r = sl; r < a.chi_r; r += W) out.put(r, 0.f, 0.f);
   }
   out.pad(a, sl, W);
+}
+
+// Measurement without displacement, in two phases per workgroup of 64 rows:
+//   1. wave 0 takes one row per lane and makes the per-row decision (branch
+//      weights from the partial sums, S, the Philox uniform, the outcome,
+//      logp, flags and emits): the scalar FP64 and 64-bit integer work is
+//      done once per row instead of once per lane of the row's group;
+//   2. the four waves gather the chosen branches of the 64 rows, scaled by
+//      1 / sqrt(q_s), and write them as the next left vectors: a row is
+//      handled by meas_lanes(chi_r) lanes, each taking 4 consecutive complex
+//      at a time, over a flat loop of (row, piece) so that several rows'
+//      loads are in flight together.
+// The arithmetic, its order and every stored value are those of the
+// one-group-per-row form used with displacement above.  RPB rows per
+// workgroup: 16 when a whole wave gathers one row (chi_r >= 253: more
+// workgroups, so that decisions of some overlap the gathers of others), 64
+// otherwise.
+template <int OUT, int RPB>
+__global__ __launch_bounds__(256) void measure_rows_kernel(const MeasureProb* probs, const ChunkArgs* chp,
+                                                           uint64_t seed, int* nflag) {
+  static_assert(RPB <= 64, "one lane of wave 0 per row in the decision phase");
+  constexpr int kRowsPerBlock = RPB;
+  __shared__ int s_sh[kRowsPerBlock];       // chosen branch, -1 if the row is flagged or past the chunk
+  __shared__ float scale_sh[kRowsPerBlock];  // 1 / sqrt(q_s)
+  const ChunkArgs ch = *chp;
+  const MeasureProb a = probs[blockIdx.y];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int row0 = blockIdx.x * kRowsPerBlock;
+  if (row0 >= ch.rows) return;  // the whole workgroup
+  const int d = a.d, T = a.T;
+
+  if (wv == 0 && lane < kRowsPerBlock) {
+    const int row = row0 + lane;
+    int sv = -1;
+    float scale = 0.f;
+    if (row < ch.rows) {
+      const int64_t crow = ch.c0 + row;
+      double* const logp = a.logp + (a.logp_in_call ? crow : row);
+      const float* qp = a.qpart + (size_t)row * (d * T);
+      double q[DMAX];
+#pragma unroll
+      for (int i = 0; i < DMAX; ++i) {
+        double qi = 0.0;
+        if (i < d)
+          for (int t = 0; t < T; ++t) qi += (double)qp[i * T + t];
+        q[i] = qi;
+      }
+      double S = 0.0;
+#pragma unroll
+      for (int i = 0; i < DMAX; ++i)
+        if (i < d) S += q[i];
+      const double lp_prev = *logp;
+      const bool alive = !(lp_prev == -INFINITY);
+      bool ok = alive && isfinite(S) && S > 0.0;
+      const double u = draw_uniform((uint64_t)(ch.n_offset + crow), a.site, seed, a.mps_id);
+      int s = 0;
+      double Pi = 0.0;
+#pragma unroll
+      for (int i = 0; i < DMAX; ++i) {
+        Pi += q[i];
+        if (i < d && u > Pi / S) ++s;
+      }
+      if (s > d - 1) s = d - 1;
+      double qs = 0.0;
+#pragma unroll
+      for (int i = 0; i < DMAX; ++i)
+        if (i == s) qs = q[i];
+      ok = ok && qs > 0.0;
+      if (!ok) s = 0;
+      a.outcomes[(size_t)crow * a.M + a.site] = ok ? s : -1;
+      *logp = ok ? lp_prev + (log(qs) - log(S)) : -INFINITY;
+      if (alive && !ok) atomicAdd(nflag, 1);
+      if (crow < a.emit_n) {
+        if (a.emit_u) a.emit_u[(size_t)crow * a.M + a.site] = u;
+        if (a.emit_probs) {
+          double* ep = a.emit_probs + ((size_t)crow * a.M + a.site) * a.emit_dmax;
+#pragma unroll
+          for (int i = 0; i < DMAX; ++i)
+            if (i < d && i < a.emit_dmax) ep[i] = ok ? q[i] / S : NAN;
+        }
+      }
+      if (ok) {
+        sv = s;
+        scale = (float)(1.0 / sqrt(qs));
+      } else {
+        sv = d;  // flagged: the next left vector is zero
+      }
+    }
+    s_sh[lane] = sv;
+    scale_sh[lane] = scale;
+  }
+  __syncthreads();
+
+  const int W = meas_lanes(a.chi_r);  // lanes per row
+  const int G = 64 / W;               // rows per wave step
+  const int g = lane / W, sl = lane & (W - 1);
+  const int nq = (a.chi_r + 3) >> 2;  // pieces of 4 complex per row
+  const int iters = (nq + W - 1) / W;
+  const int nsteps = (kRowsPerBlock + 4 * G - 1) / (4 * G);
+  const bool even = (a.chi_r & 1) == 0;  // a piece is then 16-byte aligned
+#pragma unroll 4
+  for (int t = 0; t < nsteps * iters; ++t) {
+    const int k = t / iters, it = t - k * iters;
+    const int rloc = (k * 4 + wv) * G + g;
+    const int q4 = sl + it * W;
+    if (rloc >= kRowsPerBlock || q4 >= nq) continue;
+    const int sv = s_sh[rloc];
+    if (sv < 0) continue;
+    const int row = row0 + rloc;
+    const int r4 = 4 * q4;
+    float2 v[4];
+    if (sv < d) {
+      const float2* src = a.W + (size_t)row * d * a.chi_r + (size_t)sv * a.chi_r;
+      if (even && r4 + 4 <= a.chi_r) {
+        const float4 p0 = *reinterpret_cast<const float4*>(src + r4);
+        const float4 p1 = *reinterpret_cast<const float4*>(src + r4 + 2);
+        v[0] = make_float2(p0.x, p0.y);
+        v[1] = make_float2(p0.z, p0.w);
+        v[2] = make_float2(p1.x, p1.y);
+        v[3] = make_float2(p1.z, p1.w);
+      } else {
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) v[jj] = r4 + jj < a.chi_r ? src[r4 + jj] : make_float2(0.f, 0.f);
+      }
+      const float scale = scale_sh[rloc];
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) v[jj] = make_float2(__fmul_rn(v[jj].x, scale), __fmul_rn(v[jj].y, scale));
+    } else {
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) v[jj] = make_float2(0.f, 0.f);
+    }
+    LWriter<OUT>(a, row).put4(r4, v);
+  }
+  // K padding of the 16-bit operand rows past the written pieces
+  for (int k = 0; k < nsteps; ++k) {
+    const int rloc = (k * 4 + wv) * G + g;
+    if (rloc < kRowsPerBlock && s_sh[rloc] >= 0) LWriter<OUT>(a, row0 + rloc).pad_from(8 * nq, sl, W);
+  }
 }
 
 // chi_0 = 1 (the open left end): every left vector is [1].  FP32: one
@@ -412,27 +551,31 @@ hipError_t launch_zero_int(int* p, int n, hipStream_t s) {
 }
 
 template <int OUT>
-void launch_measure_t(bool displaced, dim3 grid, const MeasureProb* probs, const ChunkArgs* ch, uint64_t seed,
-                      int* nflag, hipStream_t s) {
-  if (displaced)
-    hipLaunchKernelGGL((measure_kernel<OUT, true>), grid, dim3(256), 0, s, probs, ch, seed, nflag);
+void launch_measure_t(bool displaced, bool wide, int grid_rows, int nprob, const MeasureProb* probs,
+                      const ChunkArgs* ch, uint64_t seed, int* nflag, hipStream_t s) {
+  if (displaced)  // one wave per row
+    hipLaunchKernelGGL((measure_kernel<OUT, true>), dim3((grid_rows + 3) / 4, nprob), dim3(256), 0, s, probs, ch,
+                       seed, nflag);
+  else if (wide)
+    hipLaunchKernelGGL((measure_rows_kernel<OUT, 16>), dim3((grid_rows + 15) / 16, nprob), dim3(256), 0, s, probs,
+                       ch, seed, nflag);
   else
-    hipLaunchKernelGGL((measure_kernel<OUT, false>), grid, dim3(256), 0, s, probs, ch, seed, nflag);
+    hipLaunchKernelGGL((measure_rows_kernel<OUT, 64>), dim3((grid_rows + 63) / 64, nprob), dim3(256), 0, s, probs,
+                       ch, seed, nflag);
 }
 
 hipError_t launch_measure(int form, const MeasureProb* probs, int nprob, const ChunkArgs* ch, int grid_rows,
                           uint64_t seed, int* nflag, bool displaced, int rows_per_wave, hipStream_t s) {
   if (grid_rows <= 0 || nprob <= 0) return hipSuccess;
-  const int rpw = displaced ? 1 : (rows_per_wave < 1 ? 1 : rows_per_wave);
-  const dim3 grid((grid_rows + 4 * rpw - 1) / (4 * rpw), nprob);
+  const bool wide = rows_per_wave <= 1;  // a whole wave per row for the largest chi_r of the launch
   if (form == 0)
-    launch_measure_t<kOutF32>(displaced, grid, probs, ch, seed, nflag, s);
+    launch_measure_t<kOutF32>(displaced, wide, grid_rows, nprob, probs, ch, seed, nflag, s);
   else if (form == kBf16x3)
-    launch_measure_t<kOutBf16x2>(displaced, grid, probs, ch, seed, nflag, s);
+    launch_measure_t<kOutBf16x2>(displaced, wide, grid_rows, nprob, probs, ch, seed, nflag, s);
   else if (form == kFp16x3)
-    launch_measure_t<kOutF16x2>(displaced, grid, probs, ch, seed, nflag, s);
+    launch_measure_t<kOutF16x2>(displaced, wide, grid_rows, nprob, probs, ch, seed, nflag, s);
   else
-    launch_measure_t<kOutF16>(displaced, grid, probs, ch, seed, nflag, s);
+    launch_measure_t<kOutF16>(displaced, wide, grid_rows, nprob, probs, ch, seed, nflag, s);
   return hipGetLastError();
 }
 
