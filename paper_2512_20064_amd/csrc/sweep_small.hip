@@ -43,6 +43,8 @@ constexpr int LIM = CHI * LP + 32;  // offset of the imaginary plane
 constexpr int AP = 2 * NC;          // floats per staged site-tensor row
 constexpr int NTHR = 256;
 constexpr int NT = (NC / 16 + 3) / 4;  // column blocks per wave
+constexpr int SPT = KS * NC / NTHR;     // staged site-tensor entries per thread and stage
+static_assert(KS * NC % NTHR == 0, "the stage grid splits evenly over the threads");
 static_assert(R == 32, "one 32-row MFMA block per workgroup");
 static_assert(NC / 16 <= NT * (NTHR / 64), "the four waves cover every column block of W");
 
@@ -51,7 +53,7 @@ __global__ __launch_bounds__(NTHR, 2) void sweep_small_kernel(const SmallChain* 
                                                               int* nflag) {
   __shared__ float Ls[LIM + CHI * LP];  // left vectors: [l][row], real plane then imaginary plane
   __shared__ float2 Ws[R * NC];         // W[row][c], c = i * chi_r + r
-  __shared__ float As[KS * AP];         // one stage of the site tensor: [l][2c + part]
+  __shared__ __attribute__((aligned(16))) float As[KS * AP];  // one stage of the site tensor: [l][2c + part]
   __shared__ double lps[R];             // running log-probability per sample
 
   const ChunkArgs ch = *chp;
@@ -81,11 +83,24 @@ __global__ __launch_bounds__(NTHR, 2) void sweep_small_kernel(const SmallChain* 
   const int64_t crow = ch.c0 + grow;           // row within the call
   const floatx16 zero = {};
 
+  // One stage of site tensor A (K rows of ncols complex), rows l0 .. l0+15,
+  // into registers: a fixed 16 x NC grid, zeros outside the tensor.  All the
+  // loads are issued before any result is used, so their latencies overlap.
+  float2 sv[SPT];
+  auto load_stage = [&](const float2* A, int K, int ncols, int l0) {
+#pragma unroll
+    for (int it = 0; it < SPT; ++it) {
+      const int e = tid + it * NTHR;
+      const int ll = e / NC, cc = e % NC;
+      const int l = l0 + ll;
+      sv[it] = (l < K && cc < ncols) ? A[(size_t)l * ncols + cc] : make_float2(0.f, 0.f);
+    }
+  };
+
   for (int k = 0; k < c.M; ++k) {
     const int K = c.chi[k], dk = c.d[k], cr = c.chi[k + 1];
     const int ncols = dk * cr;
     const int nblk = (ncols + 15) >> 4;  // 16 complex = 32 real columns per MFMA block
-    const int cpad = nblk * 16;
     const float2* A = c.A[k];
 
     floatx16 tot[NT], blk[NT];
@@ -93,13 +108,13 @@ __global__ __launch_bounds__(NTHR, 2) void sweep_small_kernel(const SmallChain* 
     for (int t = 0; t < NT; ++t) tot[t] = zero;
 
     for (int l0 = 0; l0 < K; l0 += KS) {
+      load_stage(A, K, ncols, l0);
       __syncthreads();  // previous stage (or the previous site's measurement) done with LDS
-      for (int e = tid; e < KS * cpad; e += NTHR) {
-        const int ll = e / cpad, cc = e - ll * cpad;
-        const int l = l0 + ll;
-        const float2 v = (l < K && cc < ncols) ? A[(size_t)l * ncols + cc] : make_float2(0.f, 0.f);
-        As[ll * AP + 2 * cc] = v.x;
-        As[ll * AP + 2 * cc + 1] = v.y;
+#pragma unroll
+      for (int it = 0; it < SPT; ++it) {
+        const int e = tid + it * NTHR;
+        const int ll = e / NC, cc = e % NC;
+        *reinterpret_cast<float2*>(&As[ll * AP + 2 * cc]) = sv[it];
       }
       __syncthreads();
 #pragma unroll
