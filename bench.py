@@ -382,11 +382,12 @@ def run_stream_bench(args):
             "expand_ms": round(st.expand_ms, 1), "overlap": None if overlap is None else round(overlap, 4),
             "copy_share_of_wall": round(copy_ms / (dt * 1e3), 4),
         },
-        # a complex-fp16 site is exact in fp16: the fp16 split form skips the
-        # product with the (zero) low parts of the site tensor
+        # complex-fp16 sites, and complex-fp8 sites with power-of-two block
+        # scales (the encoder's choice), expand to values exact in fp16: the
+        # fp16 split form skips the product with the (zero) low parts
         "roofline": (roofline_of(args.precision, st.contract_flops, st.contract_launches, st.contract_ms,
                                  dt, st.measure_ms, st.pack_ms, args.chunk,
-                                 products=2 if (args.precision == "fp16x3" and kind == "cf16") else None)
+                                 products=2 if (args.precision == "fp16x3" and kind in ("cf16", "cf8")) else None)
                      if st.contract_ms > 0 else None),
         "cpu_baseline": None,
     }

@@ -74,6 +74,16 @@ enum {
  *             block of the chi[k] x d[k]*chi[k+1] complex matrix, row-major
  *             over blocks; an entry is its code's value times its block's
  *             scale.
+ * With MPS_FP16X3, sites whose expanded values are exact binary16 values are
+ * contracted with two MFMA products per complex product instead of three
+ * (the low parts of the site tensor are zero; the result is bit-identical):
+ * every MPS_CF16 site, and every MPS_CF8 site in pinned host memory whose
+ * block scales are all powers of two 2^e (as with microscaling encoders)
+ * with exponents spanning at most 22.  Such an fp8 site is expanded times
+ * 2^t, the t that brings every exponent into [-15, 7] (where code * 2^e is
+ * on the binary16 grid): the sampled outcomes, the conditional
+ * probabilities, the next left vectors and logp = sum ln(q_s / S) are
+ * exactly invariant to that per-site power of two.
  * A site pointer may be device memory or pinned host memory (hipHostMalloc);
  * pageable host memory is rejected (MPS_EINVAL).  Host sites are copied to
  * the device on a side stream of the handle, one site ahead of the compute

@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void decompress_kernel(DecompressProb p) {
     } else {
       const unsigned char* b = (const unsigned char*)p.src;
       const float* scales = (const float*)(b + (2 * n + 255) / 256 * 256);
-      const float sc = scales[(size_t)(l >> 7) * nbc + (c >> 7)];
+      const float sc = scales[(size_t)(l >> 7) * nbc + (c >> 7)] * p.scale_mul;
       const unsigned short pair = ((const unsigned short*)b)[i];
       v = make_float2(e4m3_to_float(pair & 0xFF) * sc, e4m3_to_float(pair >> 8) * sc);
     }

@@ -6,7 +6,8 @@
 //   P_j   = q_0 + ... + q_j (left to right), S = P_{d-1}, C_j = P_j / S;
 //   u     = uniform from Philox4x64-10 at (seed, chain, global sample, site);
 //   s     = #{ j : u > C_j }, clamped to d-1 (strict comparison);
-//   logp += ln q_s - ln S;
+//   logp += ln(q_s / S) (one logarithm of the conditional probability: the
+//           same bits when a site tensor is scaled by a power of two);
 //   l'    = W[s, :] / sqrt(q_s), written in the operand format of the next
 //           contraction (FP32 complex, or 16-bit hi/lo planes).
 //
@@ -295,7 +296,7 @@ __global__ __launch_bounds__(256) void measure_kernel(const MeasureProb* probs, 
 
   if (sl == 0) {
     a.outcomes[(size_t)crow * a.M + a.site] = ok ? s : -1;
-    *logp = ok ? lp_prev + (log(qs) - log(S)) : -INFINITY;
+    *logp = ok ? lp_prev + log(qs / S) : -INFINITY;
     if (alive && !ok) atomicAdd(nflag, 1);
     if (crow < a.emit_n) {
       if (a.emit_u) a.emit_u[(size_t)crow * a.M + a.site] = u;
@@ -424,7 +425,7 @@ __global__ __launch_bounds__(256) void measure_rows_kernel(const MeasureProb* pr
       ok = ok && qs > 0.0;
       if (!ok) s = 0;
       a.outcomes[(size_t)crow * a.M + a.site] = ok ? s : -1;
-      *logp = ok ? lp_prev + (log(qs) - log(S)) : -INFINITY;
+      *logp = ok ? lp_prev + log(qs / S) : -INFINITY;
       if (alive && !ok) atomicAdd(nflag, 1);
       if (crow < a.emit_n) {
         if (a.emit_u) a.emit_u[(size_t)crow * a.M + a.site] = u;

@@ -217,6 +217,35 @@ struct mps_ctx {
 
 namespace {
 
+// Whether a complex-fp8 site in host memory can be expanded to values that
+// are exact in fp16: every block scale a power of two 2^e, the exponents
+// within a span of 22.  An E4M3 code has at most 4 significant bits, its
+// smallest nonzero magnitude is 2^-9 and its largest 448, so code * 2^e lies
+// on the binary16 grid when -15 <= e <= 7 (lowest bit >= 2^-24, magnitude <=
+// 448 * 2^7 < 65504).  *shift receives the t that moves every exponent into
+// that range (0 if they already are): the expansion multiplies the site by
+// 2^t, a per-site constant that every conditional probability, draw and
+// renormalised left vector is invariant to, exactly (W, q and S scale by
+// powers of two; logp is ln(q_s / S)).
+bool cf8_fp16_shift(const void* host, int chi_l, int d, int chi_r, int* shift) {
+  const size_t n = (size_t)chi_l * d * chi_r;
+  const size_t off = (2 * n + 255) / 256 * 256;
+  const size_t nb = (size_t)((chi_l + 127) / 128) * (size_t)(((size_t)d * chi_r + 127) / 128);
+  const unsigned char* sp = (const unsigned char*)host + off;
+  int emin = 1 << 20, emax = -(1 << 20);
+  for (size_t i = 0; i < nb; ++i) {
+    uint32_t b;
+    std::memcpy(&b, sp + 4 * i, 4);
+    const int field = (int)((b >> 23) & 0xFF);
+    if ((b & 0x807FFFFFu) != 0 || field == 0 || field == 0xFF) return false;  // not a positive normal power of two
+    emin = std::min(emin, field - 127);
+    emax = std::max(emax, field - 127);
+  }
+  if (nb == 0 || emax - emin > 22) return false;
+  *shift = emin < -15 ? -15 - emin : (emax > 7 ? 7 - emax : 0);
+  return true;
+}
+
 // Where a site pointer lives.  A batch can hold tens of thousands of site
 // tensors, most of them in a few allocations: each allocation is asked about
 // once (hipPointerGetAttributes for the memory type, hipMemGetAddressRange for
@@ -311,7 +340,8 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
   // another stored form is expanded on the device into one of two slots (by
   // site parity); a host-resident site is first copied, on the side stream,
   // into one of two copy slots, one site ahead of the computation.
-  std::vector<char> host_site(single ? Mmax : 0, 0), staged(single ? Mmax : 0, 0);
+  std::vector<char> host_site(single ? Mmax : 0, 0), staged(single ? Mmax : 0, 0), fp16_exact(single ? Mmax : 0, 0);
+  std::vector<int> fp16_shift(single ? Mmax : 0, 0);  // power of two applied to an expanded fp8 site
   size_t dec_max = 0, comp_max = 0;
   bool any_staged = false;
   PtrClassifier where;
@@ -336,6 +366,8 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
       }
       host_site[k] = on_host;
       staged[k] = on_host || kind != MPS_C64;
+      fp16_exact[k] = kind == MPS_CF16 ||
+                      (kind == MPS_CF8 && on_host && cf8_fp16_shift(c.tensors[k], c.chi[k], c.d[k], c.chi[k + 1], &fp16_shift[k]));
       any_staged = any_staged || staged[k];
       if (staged[k]) dec_max = std::max(dec_max, (size_t)c.chi[k] * c.d[k] * c.chi[k + 1] * sizeof(float2));
       if (on_host) comp_max = std::max(comp_max, mps::stored_bytes(kind, c.chi[k], c.d[k], c.chi[k + 1]));
@@ -638,11 +670,12 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
     MPS_HIP(mps::launch_init(form, (const mps::InitProb*)tp(init_off[s]), B, ch, grid_rows, stream), "init kernel");
     return MPS_OK;
   };
-  // A complex-fp16 stored site holds exact fp16 values: in the fp16 split
-  // form the low parts of its embedding are zero and one of the three
-  // products is skipped (bit-identical result).
+  // A site whose expanded values are exact fp16 values (complex-fp16, or
+  // complex-fp8 with qualifying block scales, expanded with its power-of-two
+  // shift): in the fp16 split form the low parts of its embedding are zero
+  // and one of the three products is skipped (bit-identical result).
   auto site_form = [&](int k) {
-    return single && form == mps::kFp16x3 && kind == MPS_CF16 && staged[k] ? (int)mps::kFp16x2 : form;
+    return single && form == mps::kFp16x3 && staged[k] && fp16_exact[k] ? (int)mps::kFp16x2 : form;
   };
   auto run_pack = [&](int k) -> int {
     if (!lowp) return MPS_OK;
@@ -692,7 +725,8 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
       src = comp_slot[k & 1];
     }
     MPS_TRY(mark(k, 8, stream));
-    mps::DecompressProb dp{src, dec_slot[k & 1], c.chi[k], c.d[k], c.chi[k + 1], kind};
+    const float scale_mul = kind == MPS_CF8 && site_form(k) == mps::kFp16x2 ? std::ldexp(1.f, fp16_shift[k]) : 1.f;
+    mps::DecompressProb dp{src, dec_slot[k & 1], c.chi[k], c.d[k], c.chi[k + 1], kind, scale_mul};
     MPS_HIP(mps::launch_decompress(dp, stream), "expand launch");
     MPS_TRY(mark(k, 9, stream));
     MPS_HIP(hipEventRecord(h->ev_expand[k & 1], stream), "hipEventRecord");

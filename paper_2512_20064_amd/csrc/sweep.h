@@ -153,7 +153,8 @@ struct DecompressProb {
   const void* src;
   float2* dst;
   int chi_l, d, chi_r;
-  int kind;  // 0 complex64, 1 complex-fp16, 2 complex-fp8 with 128x128 block scales
+  int kind;         // 0 complex64, 1 complex-fp16, 2 complex-fp8 with 128x128 block scales
+  float scale_mul;  // complex-fp8: a power of two multiplying every block scale (1: none)
 };
 size_t stored_bytes(int kind, int chi_l, int d, int chi_r);
 hipError_t launch_decompress(const DecompressProb& p, hipStream_t s);

@@ -197,7 +197,7 @@ __global__ __launch_bounds__(NTHR, 2) void sweep_small_kernel(const SmallChain* 
     ok = ok && qs > 0.0;
     if (!ok) s = 0;
     if (sl == 0) {
-      lps[mrow] = ok ? lp_prev + (log(qs) - log(S)) : -INFINITY;
+      lps[mrow] = ok ? lp_prev + log(qs / S) : -INFINITY;
       if (valid) {
         c.outcomes[(size_t)crow * c.M + k] = ok ? s : -1;
         if (alive && !ok) atomicAdd(nflag, 1);

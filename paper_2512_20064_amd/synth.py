@@ -197,12 +197,24 @@ def promote(tensors: list[np.ndarray]) -> list[np.ndarray]:
 #                 entry, followed (at the next multiple of 256 bytes) by FP32
 #                 scales, one per 128 x 128 block of the chi_l x (d*chi_r)
 #                 complex matrix, row-major over blocks; an entry decodes to
-#                 code_value * scale of its block.  Scales map each block's
-#                 largest |re| or |im| to 448 (the largest E4M3 value).
+#                 code_value * scale of its block.  Each scale is the
+#                 smallest power of two that brings the block's largest |re|
+#                 or |im| to at most 448 (the largest E4M3 value), as the
+#                 OCP microscaling formats do: then every decoded value is
+#                 exactly representable in binary16 (for scale exponents in
+#                 [-15, 7]), which the sampler's fp16 split form exploits.
 # --------------------------------------------------------------------------
 
 FP8_BLOCK = 128
 E4M3_MAX = 448.0
+
+
+def fp8_block_scale(amax: float) -> np.float32:
+    """Smallest power of two s with amax / s <= 448 (1 for an all-zero block)."""
+    if not amax > 0:
+        return np.float32(1.0)
+    m, e = np.frexp(np.float64(amax) / E4M3_MAX)  # amax / 448 = m 2^e, 0.5 <= m < 1
+    return np.float32(np.ldexp(1.0, int(e) - 1 if m == 0.5 else int(e)))
 
 
 def _e4m3_grid() -> np.ndarray:
@@ -259,7 +271,7 @@ def compress_site(A: np.ndarray, kind: str) -> np.ndarray:
             for bj in range(nbc):
                 blk = mat[bi * FP8_BLOCK:(bi + 1) * FP8_BLOCK, bj * FP8_BLOCK:(bj + 1) * FP8_BLOCK]
                 amax = float(max(np.abs(blk.real).max(), np.abs(blk.imag).max()))
-                sc = np.float32(amax / E4M3_MAX) if amax > 0 else np.float32(1.0)
+                sc = fp8_block_scale(amax)
                 scales[bi, bj] = sc
                 sl = (slice(bi * FP8_BLOCK, (bi + 1) * FP8_BLOCK), slice(bj * FP8_BLOCK, (bj + 1) * FP8_BLOCK))
                 codes[sl + (0,)] = encode_e4m3(blk.real / np.float64(sc))
@@ -352,8 +364,8 @@ def structured_chain(tensor_seed: int, d: list[int], chi_max: int, pool: int = 4
 def compress_site_torch(A, kind: str):
     """compress_site for a complex64 torch tensor on any device (same bytes:
     binary16 by torch's round-to-nearest-even cast, E4M3 by the same
-    nearest-even search over the code values as encode_e4m3, block scales
-    formed in float64 and rounded to float32 once)."""
+    nearest-even search over the code values as encode_e4m3, the same
+    power-of-two block scales)."""
     import torch
     A = A.contiguous()
     chi_l, d, chi_r = A.shape
@@ -379,8 +391,9 @@ def compress_site_torch(A, kind: str):
         r = slab.shape[0]
         padc = nbc * FP8_BLOCK - ncol
         amax = torch.nn.functional.pad(slab.abs().amax(dim=2), (0, padc)).view(r, nbc, FP8_BLOCK).amax(dim=(0, 2))
-        sc = torch.where(amax > 0, (amax.to(torch.float64) / E4M3_MAX).to(torch.float32),
-                         torch.ones_like(amax))
+        m, e = torch.frexp(amax.to(torch.float64) / E4M3_MAX)
+        e = torch.where(m == 0.5, e - 1, e)
+        sc = torch.where(amax > 0, torch.ldexp(torch.ones_like(m), e).to(torch.float32), torch.ones_like(amax))
         scales[bi] = sc
         scol = sc.repeat_interleave(FP8_BLOCK)[:ncol].to(torch.float64)
         x = torch.clamp(slab.to(torch.float64) / scol[None, :, None], -E4M3_MAX, E4M3_MAX)

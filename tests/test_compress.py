@@ -73,8 +73,10 @@ def test_cf8_blocks_scales_and_error_bound(shape):
     for bi in range(nbr):
         for bj in range(nbc):
             blk = mat[bi * 128:(bi + 1) * 128, bj * 128:(bj + 1) * 128]
-            amax = max(np.abs(blk.real).max(), np.abs(blk.imag).max())
-            assert scales[bi, bj] == np.float32(float(amax) / 448.0)
+            amax = float(max(np.abs(blk.real).max(), np.abs(blk.imag).max()))
+            # the smallest power of two that brings the block maximum to <= 448
+            m, e = np.frexp(float(scales[bi, bj]))
+            assert m == 0.5 and 224.0 < amax / float(scales[bi, bj]) <= 448.0
     dec = decode_site(raw, shape, "cf8").reshape(chi_l, d * chi_r)
     sc = np.repeat(np.repeat(scales.astype(np.float64), 128, 0), 128, 1)[:chi_l, :d * chi_r]
     for part in (np.real, np.imag):
@@ -83,9 +85,20 @@ def test_cf8_blocks_scales_and_error_bound(shape):
         # round to nearest: half a mantissa step (2^-4 relative) for normals,
         # half the subnormal step (2^-10 of the scale) below 2^-6 of the scale
         assert np.all(err <= np.maximum(np.abs(x) * 2.0 ** -4, sc * 2.0 ** -10) * (1 + 1e-6))
-    # each block's largest magnitude is stored as +-448 exactly
-    codes = raw[:2 * n].reshape(chi_l, d * chi_r, 2)
-    assert np.isin(codes, [0x7E, 0xFE]).any()
+    # every decoded value is exact in binary16 (power-of-two scales with
+    # exponents in [-15, 7], E4M3 codes of at most 4 significant bits)
+    for part in (np.real, np.imag):
+        v = part(dec)
+        assert np.array_equal(v.astype(np.float16).astype(np.float64), v)
+
+
+def test_fp8_block_scale_edges():
+    assert synth.fp8_block_scale(0.0) == 1.0
+    assert synth.fp8_block_scale(448.0) == 1.0            # exactly 448 fits
+    assert synth.fp8_block_scale(448.5) == 2.0
+    assert synth.fp8_block_scale(0.875) == 2.0 ** -9     # 0.875 / 2^-9 = 448
+    assert synth.fp8_block_scale(0.876) == 2.0 ** -8
+    assert synth.fp8_block_scale(1e-3) == 2.0 ** -18     # 1e-3 / 2^-18 = 262.1
 
 
 def test_cf16_is_numpy_binary16_and_c64_is_identity():

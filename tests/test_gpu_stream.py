@@ -87,6 +87,52 @@ def test_staged_equals_resident_expanded_tensor(form, kind, where):
     assert st.h2d_bytes == nb_host
 
 
+def _fp8_shift(raw, shape):
+    """The power of two t that the library applies to a complex-fp8 site with
+    power-of-two block scales (every exponent brought into [-15, 7]), restated
+    from its documented rule."""
+    chi_l, d, chi_r = shape
+    n = chi_l * d * chi_r
+    off = -(-2 * n // 256) * 256
+    nb = -(-chi_l // 128) * -(-(d * chi_r) // 128)
+    sc = raw[off:off + 4 * nb].view(np.float32).astype(np.float64)
+    m, e = np.frexp(sc)
+    assert np.all(m == 0.5)  # powers of two
+    e = e - 1
+    assert e.max() - e.min() <= 22
+    return -15 - e.min() if e.min() < -15 else (7 - e.max() if e.max() > 7 else 0)
+
+
+def test_small_magnitude_fp8_sites_in_the_two_product_form():
+    """Complex-fp8 sites whose block scales lie below 2^-15 (entries of order
+    2^-15 here) are expanded times 2^t so that they sit on the binary16 grid
+    and take the two-product fp16 contraction: the staged call is
+    bit-identical to a resident fp16x3 call on the expanded tensors times
+    2^t, and its draws and conditional probabilities match the oracle on the
+    unshifted values (they are invariant to a per-site power of two)."""
+    from paper_2512_20064_amd import mps
+    from tests.parity_util import compare, upload, EPS_LOWP
+    print("[gpu-case] small-magnitude cf8 host sites, fp16x3, shifted expansion", flush=True)
+    ch = [np.ascontiguousarray(t * np.float32(2.0 ** -12)) for t in _chain()]
+    shapes = [t.shape for t in ch]
+    raws = [synth.compress_site(t, "cf8") for t in ch]
+    shifts = [_fp8_shift(r, sh) for r, sh in zip(raws, shapes)]
+    assert max(shifts) > 0
+    expanded = [_expand_f32(r, sh, "cf8") for r, sh in zip(raws, shapes)]
+    shifted = [np.ascontiguousarray(x * np.float32(2.0 ** t)) for x, t in zip(expanded, shifts)]
+    N, seed = 1000, 707
+    s = mps.Sampler(0, n_chunk=256, precision="fp16x3", fused_small=False)
+    ref = s.sample(upload(shifted), N, seed)
+    got = s.sample_stored(_stored(ch, "cf8", "host"), shapes, "cf8", N, seed, emit_n=200)
+    torch.cuda.synchronize()
+    s.close()
+    assert torch.equal(got["outcomes"], ref["outcomes"])
+    assert torch.equal(got["logp"], ref["logp"])
+    gpu = {k: v.cpu().numpy() for k, v in got.items() if k != "status"}
+    rep = compare(expanded, seed, gpu, rows=np.arange(200), eps=EPS_LOWP)
+    print(rep, flush=True)
+
+
 @pytest.mark.parametrize("kind,form", [("cf16", "fp32"), ("cf8", "fp32"), ("cf16", "fp16x3"), ("cf8", "fp16x3")])
 def test_staged_parity_with_oracle(kind, form):
     """Compressed pinned-host sites against the FP64 oracle run on the same
