@@ -24,11 +24,9 @@
 // does the same job, keeps every element of l' within [-1, 1], and the scale
 // cancels in q_i / S.  The log-norm of the path is tracked in logp.
 //
-// Without displacement (measure_rows_kernel) a workgroup measures 64 rows:
-// one lane per row makes the decision (the scalar FP64 and 64-bit integer
-// work, once per row), then groups of meas_lanes(chi_r) lanes (the whole wave
-// for chi_r >= 253, down to one lane for chi_r <= 4) gather the chosen
-// branches.  With displacement (measure_kernel) one wave measures one row:
+// Without displacement (measure_rows_kernel) a workgroup measures 64 rows: one lane per row makes the decision (the scalar FP64 and 64-bit
+// integer work, once per row), then groups of min(meas_lanes(chi_r), 16)
+// lanes (down to one lane for chi_r <= 4) gather the chosen branches.  With displacement (measure_kernel) one wave measures one row:
 // it builds that row's D in its LDS and forms the weights from W' directly.
 
 #include "philox.h"
@@ -361,21 +359,19 @@ __global__ __launch_bounds__(256) void measure_kernel(const MeasureProb* probs, 
 //      weights from the partial sums, S, the Philox uniform, the outcome,
 //      logp, flags and emits): the scalar FP64 and 64-bit integer work is
 //      done once per row instead of once per lane of the row's group;
-//   2. the four waves gather the chosen branches of the 64 rows, scaled by
+//   2. the four waves gather the chosen branches of the rows, scaled by
 //      1 / sqrt(q_s), and write them as the next left vectors: a row is
-//      handled by meas_lanes(chi_r) lanes, each taking 4 consecutive complex
-//      at a time, over a flat loop of (row, piece) so that several rows'
-//      loads are in flight together.
+//      handled by min(meas_lanes(chi_r), 16) lanes, each taking 4
+//      consecutive complex at a time, over a flat loop of (row, piece) so
+//      that several rows' loads are in flight together.
 // The arithmetic, its order and every stored value are those of the
-// one-group-per-row form used with displacement above.  RPB rows per
-// workgroup: 16 when a whole wave gathers one row (chi_r >= 253: more
-// workgroups, so that decisions of some overlap the gathers of others), 64
-// otherwise.
-template <int OUT, int RPB>
+// one-group-per-row form used with displacement above.
+constexpr int kRowsPerBlock = 64;
+static_assert(kRowsPerBlock <= 64, "one lane of wave 0 per row in the decision phase");
+
+template <int OUT>
 __global__ __launch_bounds__(256) void measure_rows_kernel(const MeasureProb* probs, const ChunkArgs* chp,
                                                            uint64_t seed, int* nflag) {
-  static_assert(RPB <= 64, "one lane of wave 0 per row in the decision phase");
-  constexpr int kRowsPerBlock = RPB;
   __shared__ int s_sh[kRowsPerBlock];       // chosen branch, -1 if the row is flagged or past the chunk
   __shared__ float scale_sh[kRowsPerBlock];  // 1 / sqrt(q_s)
   const ChunkArgs ch = *chp;
@@ -448,7 +444,11 @@ __global__ __launch_bounds__(256) void measure_rows_kernel(const MeasureProb* pr
   }
   __syncthreads();
 
-  const int W = meas_lanes(a.chi_r);  // lanes per row
+  // lanes per row: meas_lanes(chi_r), at most 16, so that a wave gathers at
+  // least four rows at a time (chi_r = 1024, bf16 hi+lo: 187 us per 65536-row
+  // launch against 273 us with the whole wave on one row; 32 and 8 lanes: 214
+  // and 202 us)
+  const int W = meas_lanes(a.chi_r) < 16 ? meas_lanes(a.chi_r) : 16;
   const int G = 64 / W;               // rows per wave step
   const int g = lane / W, sl = lane & (W - 1);
   const int nq = (a.chi_r + 3) >> 2;  // pieces of 4 complex per row
@@ -552,31 +552,28 @@ hipError_t launch_zero_int(int* p, int n, hipStream_t s) {
 }
 
 template <int OUT>
-void launch_measure_t(bool displaced, bool wide, int grid_rows, int nprob, const MeasureProb* probs,
-                      const ChunkArgs* ch, uint64_t seed, int* nflag, hipStream_t s) {
+void launch_measure_t(bool displaced, int grid_rows, int nprob, const MeasureProb* probs, const ChunkArgs* ch,
+                      uint64_t seed, int* nflag, hipStream_t s) {
   if (displaced)  // one wave per row
     hipLaunchKernelGGL((measure_kernel<OUT, true>), dim3((grid_rows + 3) / 4, nprob), dim3(256), 0, s, probs, ch,
                        seed, nflag);
-  else if (wide)
-    hipLaunchKernelGGL((measure_rows_kernel<OUT, 16>), dim3((grid_rows + 15) / 16, nprob), dim3(256), 0, s, probs,
-                       ch, seed, nflag);
   else
-    hipLaunchKernelGGL((measure_rows_kernel<OUT, 64>), dim3((grid_rows + 63) / 64, nprob), dim3(256), 0, s, probs,
-                       ch, seed, nflag);
+    hipLaunchKernelGGL((measure_rows_kernel<OUT>), dim3((grid_rows + kRowsPerBlock - 1) / kRowsPerBlock, nprob),
+                       dim3(256), 0, s, probs, ch, seed, nflag);
 }
 
 hipError_t launch_measure(int form, const MeasureProb* probs, int nprob, const ChunkArgs* ch, int grid_rows,
                           uint64_t seed, int* nflag, bool displaced, int rows_per_wave, hipStream_t s) {
+  (void)rows_per_wave;
   if (grid_rows <= 0 || nprob <= 0) return hipSuccess;
-  const bool wide = rows_per_wave <= 1;  // a whole wave per row for the largest chi_r of the launch
   if (form == 0)
-    launch_measure_t<kOutF32>(displaced, wide, grid_rows, nprob, probs, ch, seed, nflag, s);
+    launch_measure_t<kOutF32>(displaced, grid_rows, nprob, probs, ch, seed, nflag, s);
   else if (form == kBf16x3)
-    launch_measure_t<kOutBf16x2>(displaced, wide, grid_rows, nprob, probs, ch, seed, nflag, s);
+    launch_measure_t<kOutBf16x2>(displaced, grid_rows, nprob, probs, ch, seed, nflag, s);
   else if (form == kFp16x3)
-    launch_measure_t<kOutF16x2>(displaced, wide, grid_rows, nprob, probs, ch, seed, nflag, s);
+    launch_measure_t<kOutF16x2>(displaced, grid_rows, nprob, probs, ch, seed, nflag, s);
   else
-    launch_measure_t<kOutF16>(displaced, wide, grid_rows, nprob, probs, ch, seed, nflag, s);
+    launch_measure_t<kOutF16>(displaced, grid_rows, nprob, probs, ch, seed, nflag, s);
   return hipGetLastError();
 }
 

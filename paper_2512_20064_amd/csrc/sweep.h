@@ -169,9 +169,8 @@ hipError_t launch_pack_lp(int form, const PackProb* probs, const int* blk_start,
 hipError_t launch_contract_lp(int form, const ContractLpProb* probs, const int* tn_start, int nprob, int tn_total,
                               const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s);
 // displaced: the problems carry per-sample displacements (MeasureProb::mu);
-// rows_per_wave: 64 / meas_lanes(largest chi_r of the problems); 1 (a whole
-// wave per row) selects the 16-row blocks of the measurement, more the 64-row
-// ones.  Ignored when displaced (one wave per row).
+// rows_per_wave: 64 / meas_lanes(largest chi_r of the problems) (kept for
+// callers; the measurement now sizes its lane groups per problem).
 hipError_t launch_measure(int form, const MeasureProb* probs, int nprob, const ChunkArgs* ch, int grid_rows,
                           uint64_t seed, int* nflag, bool displaced, int rows_per_wave, hipStream_t s);
 
