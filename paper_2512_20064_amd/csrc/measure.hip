@@ -24,10 +24,12 @@
 // does the same job, keeps every element of l' within [-1, 1], and the scale
 // cancels in q_i / S.  The log-norm of the path is tracked in logp.
 //
-// Without displacement (measure_rows_kernel) a workgroup measures 64 rows: one lane per row makes the decision (the scalar FP64 and 64-bit
-// integer work, once per row), then groups of min(meas_lanes(chi_r), 16)
-// lanes (down to one lane for chi_r <= 4) gather the chosen branches.  With displacement (measure_kernel) one wave measures one row:
-// it builds that row's D in its LDS and forms the weights from W' directly.
+// Without displacement (measure_rows_kernel) a workgroup measures 64 rows:
+// one lane per row makes the decision (the scalar FP64 and 64-bit integer
+// work, once per row), then groups of min(meas_lanes(chi_r), 16) lanes (down
+// to one lane for chi_r <= 4) gather the chosen branches.  With displacement
+// (measure_kernel) one wave measures one row: it builds that row's D in its
+// LDS and forms the weights from W' directly.
 
 #include "philox.h"
 #include "sweep.h"
