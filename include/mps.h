@@ -57,7 +57,12 @@ enum {
                         vectors and the site tensor; W = Lh*Ah + Lh*Al + Ll*Ah on
                         v_mfma_f32_32x32x16_bf16                                   */
   MPS_FP16 = 2,      /* one fp16 product on v_mfma_f32_32x32x16_f16, left vectors
-                        renormalised per sample (entries within [-1, 1])           */
+                        renormalised per sample (entries within [-1, 1]).  NOT
+                        accurate to 1e-3 in the conditional probabilities: both
+                        operands carry 11-bit significands, and on the chi = 1024,
+                        d = 4 chain the error against an FP64 evaluation reaches
+                        3.3e-3 within 32 sites.  Kept as a measured speed/accuracy
+                        point; use MPS_BF16X3 or MPS_FP16X3 for the 1e-3 bar.      */
   MPS_FP16X3 = 3     /* split precision in fp16: x = hi + lo (fp16 each), three
                         products as MPS_BF16X3 on v_mfma_f32_32x32x16_f16; 11-bit
                         parts (22 bits together) but a narrower exponent range:

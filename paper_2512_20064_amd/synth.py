@@ -298,20 +298,38 @@ def compressed_bytes(chi_l: int, d: int, chi_r: int, kind: str) -> int:
 # --------------------------------------------------------------------------
 # Large-bond workloads (chi in the thousands).  A QR of a chi x d*chi matrix
 # per distinct tensor takes minutes to hours on the host at these sizes, so
-# these tensors are built directly with orthonormal rows from discrete
-# Fourier rows with random phases, on any torch device:
+# these tensors are built directly with orthonormal rows, on any torch
+# device, from discrete Fourier rows with random phases:
 #
-# * chi_l <= chi_r:  B[:, i, :] = c_i * diag(e^{i a_i}) F[:chi_l, :] diag(e^{i b_i}),
-#   F the unitary DFT of size chi_r, c_i proportional to exp(-i/2) with
-#   sum_i c_i^2 = 1; rows of F are orthonormal, so sum_i B_i B_i^H = I and
-#   branch i carries weight c_i^2 (the decaying photon-number profile);
+# * chi_l <= chi_r: the bonds are cut into nb equal blocks (nb = 4 when both
+#   bonds are multiples of 4 and chi_l >= 64, else 1).  Branch i maps left
+#   block a to right block (a + i) mod nb with weight T[a][i] = c_{(a+i) mod d}^2,
+#   c_i proportional to exp(-i/2) with sum_i c_i^2 = 1 (the decaying
+#   photon-number profile, cyclically shifted per block):
+#       B[L_a, i, R_(a+i)%nb] = sqrt(T[a][i]) diag(e^{i alpha}) F[:|L_a|, :] diag(e^{i beta}),
+#   F the unitary DFT of the block size.  For every i the map a -> (a+i) mod nb
+#   is a permutation, so rows of different left blocks never meet in one
+#   right block, and within a block sum_i T[a][i] = 1: sum_i B_i B_i^H = I.
+#   A left vector inside block a has conditionals T[a][.] exactly, and the
+#   chosen branch moves it to another block, so the conditionals depend on
+#   the prefix (a hidden Markov chain over the blocks).
 # * chi_l > chi_r (right end of a ramp, chi_l <= d*chi_r):
-#   B.reshape(chi_l, d*chi_r) = diag(e^{i a}) F[:chi_l, :] diag(e^{i b}),
+#   B.reshape(chi_l, d*chi_r) = diag(e^{i alpha}) F[:chi_l, :] diag(e^{i beta}),
 #   F the unitary DFT of size d*chi_r.
+# * Then every column r of the right bond mixes the d branches with its own
+#   d x d unitary V_r (the Q of I + 0.3 G_r, G_r complex Gaussian, diag(R)
+#   made real and positive): B'[l, i, r] = sum_j B[l, j, r] V_r[j, i].  The
+#   reshaped rows stay orthonormal (block-diagonal unitary on the right), and
+#   the branch weights now also depend on how the left vector spreads over
+#   the columns, not only on its block.
 #
-# The phases come from PCG64 seeded like the Gaussian sites, so a tensor is
-# the same on every device up to the rounding of the phase evaluation.
+# The phases and mixers come from PCG64 seeded like the Gaussian sites, so a
+# tensor is the same on every device up to the rounding of its evaluation.
 # --------------------------------------------------------------------------
+
+MIX_THETA = 0.3
+HMM_BLOCKS = 4
+
 
 def _dft_rows(torch, rows: int, n: int, pa, pb, device):
     """diag(e^{i pa}) F_n[:rows, :] diag(e^{i pb}) as complex64 (rows x n)."""
@@ -325,24 +343,59 @@ def _dft_rows(torch, rows: int, n: int, pa, pb, device):
     return torch.polar(mag, ang).to(torch.complex64)
 
 
-def structured_site(seed_words: list[int], chi_l: int, d: int, chi_r: int, device="cpu"):
-    """Right-canonical complex64 torch tensor (chi_l, d, chi_r) without a QR."""
+def structured_blocks(chi_l: int, chi_r: int) -> int:
+    """Number of bond blocks of a structured site with chi_l <= chi_r."""
+    ok = chi_l >= 16 * HMM_BLOCKS and chi_l % HMM_BLOCKS == 0 and chi_r % HMM_BLOCKS == 0
+    return HMM_BLOCKS if ok else 1
+
+
+def structured_weights(d: int, nb: int) -> np.ndarray:
+    """T[a][i]: weight of branch i for a left vector in block a (rows sum to 1)."""
+    c = np.exp(-0.5 * np.arange(d))
+    c2 = c * c / np.sum(c * c)
+    return np.array([[c2[(a + i) % d] for i in range(d)] for a in range(nb)])
+
+
+def branch_mixers(seed_words: list[int], chi_r: int, d: int, theta: float = MIX_THETA) -> np.ndarray:
+    """V[r] (chi_r, d, d): per-column unitaries near the identity."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(w) for w in seed_words] + [0x313])))
+    G = (rng.standard_normal((chi_r, d, d)) + 1j * rng.standard_normal((chi_r, d, d))) / np.sqrt(2.0)
+    Q, R = np.linalg.qr(np.eye(d)[None] + theta * G)
+    dg = np.diagonal(R, axis1=1, axis2=2)
+    return Q * (dg / np.abs(dg))[:, None, :]
+
+
+def structured_site(seed_words: list[int], chi_l: int, d: int, chi_r: int, device="cpu", mix: bool = True):
+    """Right-canonical complex64 torch tensor (chi_l, d, chi_r) without a QR
+    (construction above; mix=False leaves out the per-column mixers)."""
     import torch
     assert chi_l <= d * chi_r
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(w) for w in seed_words] + [0x5D])))
     two_pi = 2.0 * np.pi
     if chi_l <= chi_r:
-        c = np.exp(-0.5 * np.arange(d))
-        c /= np.sqrt(np.sum(c * c))
-        out = torch.empty((chi_l, d, chi_r), dtype=torch.complex64, device=device)
-        for i in range(d):
-            pa = rng.uniform(0, two_pi, chi_l)
-            pb = rng.uniform(0, two_pi, chi_r)
-            out[:, i, :] = _dft_rows(torch, chi_l, chi_r, pa, pb, device) * float(c[i])
-        return out
-    pa = rng.uniform(0, two_pi, chi_l)
-    pb = rng.uniform(0, two_pi, d * chi_r)
-    return _dft_rows(torch, chi_l, d * chi_r, pa, pb, device).reshape(chi_l, d, chi_r)
+        nb = structured_blocks(chi_l, chi_r)
+        bl, br = chi_l // nb, chi_r // nb
+        T = structured_weights(d, nb)
+        out = torch.zeros((chi_l, d, chi_r), dtype=torch.complex64, device=device)
+        for a in range(nb):
+            for i in range(d):
+                b = (a + i) % nb
+                pa = rng.uniform(0, two_pi, bl)
+                pb = rng.uniform(0, two_pi, br)
+                blk = _dft_rows(torch, bl, br, pa, pb, device) * float(np.sqrt(T[a, i]))
+                out[a * bl:(a + 1) * bl, i, b * br:(b + 1) * br] = blk
+    else:
+        pa = rng.uniform(0, two_pi, chi_l)
+        pb = rng.uniform(0, two_pi, d * chi_r)
+        out = _dft_rows(torch, chi_l, d * chi_r, pa, pb, device).reshape(chi_l, d, chi_r)
+    if not mix or d == 1:
+        return out.contiguous()
+    V = torch.as_tensor(branch_mixers(seed_words, chi_r, d).astype(np.complex64), device=device)
+    mixed = torch.zeros_like(out)
+    for i in range(d):
+        for j in range(d):
+            mixed[:, i, :] += out[:, j, :] * V[:, j, i][None, :]
+    return mixed
 
 
 def structured_chain(tensor_seed: int, d: list[int], chi_max: int, pool: int = 4, device="cpu"):

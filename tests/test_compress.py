@@ -58,72 +58,53 @@ def _site(seed, shape):
     return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64) * 0.1
 
 
-@pytest.mark.parametrize("shape", [(130, 3, 50), (1, 4, 4), (128, 1, 128), (257, 2, 70)])
-def test_cf8_blocks_scales_and_error_bound(shape):
-    A = _site(3, shape)
-    raw = synth.compress_site(A, "cf8")
-    chi_l, d, chi_r = shape
-    assert raw.size == synth.compressed_bytes(chi_l, d, chi_r, "cf8")
-    n = chi_l * d * chi_r
-    off = -(-2 * n // 256) * 256
-    nbr, nbc = -(-chi_l // 128), -(-(d * chi_r) // 128)
-    assert raw.size == off + 4 * nbr * nbc
-    scales = raw[off:].view(np.float32).reshape(nbr, nbc)
-    mat = A.reshape(chi_l, d * chi_r)
-    for bi in range(nbr):
-        for bj in range(nbc):
-            blk = mat[bi * 128:(bi + 1) * 128, bj * 128:(bj + 1) * 128]
-            amax = float(max(np.abs(blk.real).max(), np.abs(blk.imag).max()))
-            # the smallest power of two that brings the block maximum to <= 448
-            m, e = np.frexp(float(scales[bi, bj]))
-            assert m == 0.5 and 224.0 < amax / float(scales[bi, bj]) <= 448.0
-    dec = decode_site(raw, shape, "cf8").reshape(chi_l, d * chi_r)
-    sc = np.repeat(np.repeat(scales.astype(np.float64), 128, 0), 128, 1)[:chi_l, :d * chi_r]
-    for part in (np.real, np.imag):
-        x = part(mat).astype(np.float64)
-        err = np.abs(part(dec) - x)
-        # round to nearest: half a mantissa step (2^-4 relative) for normals,
-        # half the subnormal step (2^-10 of the scale) below 2^-6 of the scale
-        assert np.all(err <= np.maximum(np.abs(x) * 2.0 ** -4, sc * 2.0 ** -10) * (1 + 1e-6))
-    # every decoded value is exact in binary16 (power-of-two scales with
-    # exponents in [-15, 7], E4M3 codes of at most 4 significant bits)
-    for part in (np.real, np.imag):
-        v = part(dec)
-        assert np.array_equal(v.astype(np.float16).astype(np.float64), v)
-
-
-def test_fp8_block_scale_edges():
-    assert synth.fp8_block_scale(0.0) == 1.0
-    assert synth.fp8_block_scale(448.0) == 1.0            # exactly 448 fits
-    assert synth.fp8_block_scale(448.5) == 2.0
-    assert synth.fp8_block_scale(0.875) == 2.0 ** -9     # 0.875 / 2^-9 = 448
-    assert synth.fp8_block_scale(0.876) == 2.0 ** -8
-    assert synth.fp8_block_scale(1e-3) == 2.0 ** -18     # 1e-3 / 2^-18 = 262.1
-
-
-def test_cf16_is_numpy_binary16_and_c64_is_identity():
-    A = _site(5, (20, 4, 33))
-    dec = decode_site(synth.compress_site(A, "cf16"), A.shape, "cf16")
-    assert np.array_equal(dec.real, A.real.astype(np.float16).astype(np.float64))
-    assert np.array_equal(dec.imag, A.imag.astype(np.float16).astype(np.float64))
-    assert np.array_equal(decode_site(synth.compress_site(A, "c64"), A.shape, "c64"), A.astype(np.complex128))
-    assert synth.compressed_bytes(20, 4, 33, "cf16") == 4 * 20 * 4 * 33
-
-
-@pytest.mark.parametrize("shape", [(130, 3, 50), (64, 4, 64), (257, 2, 170), (1, 4, 4)])
+@pytest.mark.parametrize("shape", [(130, 3, 50), (64, 4, 64), (257, 2, 170), (1, 4, 4), (128, 3, 256)])
 def test_structured_sites_are_right_canonical_and_torch_compression_matches(shape):
     """Large-bond generator: orthonormal rows (sum_i B_i B_i^H = I within
-    complex64 rounding), branch weights c_i^2 ~ exp(-i) where chi_l <= chi_r,
-    and the torch compressor writes the same bytes as the numpy one."""
+    complex64 rounding), with and without the branch mixers, and the torch
+    compressor writes the same bytes as the numpy one."""
     torch = pytest.importorskip("torch")
-    B = synth.structured_site([1, 2], *shape)
-    assert B.dtype == torch.complex64 and tuple(B.shape) == shape
-    Bn = B.numpy().astype(np.complex128)
-    assert synth.canonical_error(Bn) < 1e-6
-    chi_l, d, chi_r = shape
-    if chi_l <= chi_r:
-        w = np.array([np.sum(np.abs(Bn[:, i, :]) ** 2) / chi_l for i in range(d)])
-        c = np.exp(-np.arange(d)) / np.sum(np.exp(-np.arange(d)))
-        assert np.allclose(w, c, atol=1e-6)
+    for mix in (False, True):
+        B = synth.structured_site([1, 2], *shape, mix=mix)
+        assert B.dtype == torch.complex64 and tuple(B.shape) == shape
+        assert synth.canonical_error(B.numpy().astype(np.complex128)) < 1e-6
     for kind in ("c64", "cf16", "cf8"):
         assert np.array_equal(synth.compress_site(B.numpy(), kind), synth.compress_site_torch(B, kind).numpy()), kind
+
+
+@pytest.mark.parametrize("shape", [(64, 4, 64), (128, 3, 256), (256, 6, 256), (32, 4, 64)])
+def test_structured_sites_hidden_markov_weights(shape):
+    """Without mixers, a left vector inside bond block a has conditionals
+    T[a][.] = c_{(a+.) mod d}^2 exactly (c_i^2 ~ exp(-i)), whatever the vector,
+    and branch i moves it into block (a+i) mod nb; with one block (small
+    bonds) the weights are the plain profile c_i^2.  With mixers the weights
+    depend on the vector itself, not only on its block."""
+    torch = pytest.importorskip("torch")
+    chi_l, d, chi_r = shape
+    nb = synth.structured_blocks(chi_l, chi_r)
+    assert nb == (4 if chi_l >= 64 else 1)
+    B = synth.structured_site([3, 9], *shape, mix=False).numpy().astype(np.complex128)
+    Bm = synth.structured_site([3, 9], *shape, mix=True).numpy().astype(np.complex128)
+    T = synth.structured_weights(d, nb)
+    c2 = np.exp(-np.arange(d)) / np.sum(np.exp(-np.arange(d)))
+    assert np.allclose(T[0], c2) and np.allclose(T.sum(axis=1), 1.0)
+    rng = np.random.default_rng(1)
+    bl, br = chi_l // nb, chi_r // nb
+    pm = []
+    for a in range(nb):
+        for _ in range(3):
+            x = np.zeros(chi_l, complex)
+            x[a * bl:(a + 1) * bl] = rng.standard_normal(bl) + 1j * rng.standard_normal(bl)
+            x /= np.linalg.norm(x)
+            W = np.einsum("l,lir->ir", x, B)
+            q = np.sum(np.abs(W) ** 2, axis=1)
+            assert np.allclose(q / q.sum(), T[a], atol=1e-6)
+            for i in range(d):  # branch i lands in right block (a+i) mod nb only
+                b = (a + i) % nb
+                outside = np.delete(W[i], np.arange(b * br, (b + 1) * br))
+                assert np.all(np.abs(outside) < 1e-6)
+            Wm = np.einsum("l,lir->ir", x, Bm)
+            qm = np.sum(np.abs(Wm) ** 2, axis=1)
+            pm.append(qm / qm.sum())
+    pm = np.array(pm)
+    assert np.max(pm.max(axis=0) - pm.min(axis=0)) > 1e-2

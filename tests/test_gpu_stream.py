@@ -133,6 +133,61 @@ def test_small_magnitude_fp8_sites_in_the_two_product_form():
     print(rep, flush=True)
 
 
+def _with_scales(raw, shape, fn):
+    """Copy of complex-fp8 bytes with every block scale s replaced by fn(s)."""
+    chi_l, d, chi_r = shape
+    n = chi_l * d * chi_r
+    off = -(-2 * n // 256) * 256
+    nb = -(-chi_l // 128) * -(-(d * chi_r) // 128)
+    out = raw.copy()
+    sc = out[off:off + 4 * nb].view(np.float32)
+    sc[:] = fn(sc.astype(np.float64)).astype(np.float32)
+    return out
+
+
+@pytest.mark.parametrize("variant", ["non_power_of_two", "exponent_span"])
+def test_fp8_sites_off_the_fp16_grid_take_three_products(variant):
+    """Complex-fp8 host sites that do not expand onto the binary16 grid --
+    block scales that are not powers of two, or power-of-two scales whose
+    exponents span more than 22 -- are contracted with all three fp16
+    products: the staged call is bit-identical to a resident fp16x3 call on
+    the expanded tensors (which always takes three products; dropping the
+    site's low parts would change W), and matches the FP64 oracle on those
+    values at the low-precision bar."""
+    from paper_2512_20064_amd import mps
+    from tests.parity_util import compare, upload, EPS_LOWP
+    print(f"[gpu-case] cf8 host sites off the fp16 grid ({variant}), fp16x3", flush=True)
+    ch = _chain(M=10, d=4, chi=300, seed=23)
+    shapes = [t.shape for t in ch]
+    raws = []
+    for k, (t, sh) in enumerate(zip(ch, shapes)):
+        if variant == "non_power_of_two":
+            raws.append(_with_scales(synth.compress_site(t, "cf8"), sh, lambda s: s * 0.75))
+        else:
+            t2 = t.copy()
+            if sh[0] > 128:  # first row block 2^-26 smaller: its scale exponent is 26 below the others'
+                t2[:128] *= np.float32(2.0 ** -26)
+            raws.append(synth.compress_site(t2, "cf8"))
+    if variant == "non_power_of_two":
+        sc = [r[-(-(2 * np.prod(sh)) // 256) * 256:].view(np.float32) for r, sh in zip(raws, shapes)]
+        assert all((np.frexp(x.astype(np.float64))[0] != 0.5).any() for x in sc)
+    else:
+        assert any(sh[0] > 128 for sh in shapes)
+    expanded = [_expand_f32(r, sh, "cf8") for r, sh in zip(raws, shapes)]
+    stored = [torch.from_numpy(r).pin_memory() for r in raws]
+    N, seed = 1200, 515
+    s = mps.Sampler(0, n_chunk=512, precision="fp16x3", fused_small=False)
+    ref = s.sample(upload(expanded), N, seed)
+    got = s.sample_stored(stored, shapes, "cf8", N, seed, emit_n=256)
+    torch.cuda.synchronize()
+    s.close()
+    assert torch.equal(got["outcomes"], ref["outcomes"])
+    assert torch.equal(got["logp"], ref["logp"])
+    gpu = {k: v.cpu().numpy() for k, v in got.items() if k != "status"}
+    rep = compare(expanded, seed, gpu, rows=np.concatenate([np.arange(256), np.arange(N - 100, N)]), eps=EPS_LOWP)
+    print(rep, flush=True)
+
+
 @pytest.mark.parametrize("kind,form", [("cf16", "fp32"), ("cf8", "fp32"), ("cf16", "fp16x3"), ("cf8", "fp16x3")])
 def test_staged_parity_with_oracle(kind, form):
     """Compressed pinned-host sites against the FP64 oracle run on the same
