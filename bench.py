@@ -128,22 +128,72 @@ def distinct_bytes(dev):
     return int(sum(t.numel() * t.element_size() for t in {id(t): t for t in dev}.values()))
 
 
-def cpu_baseline(t128, seed, n_samples, n_sites):
-    """The FP64 oracle as it stands, on n_samples samples over the first n_sites
-    sites (a chain window with an open right end)."""
-    import oracle
+def host_info():
+    """nproc, CPU model and the BLAS library numpy runs on (threadpoolctl)."""
+    info = {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cpu_model": None, "blas": None}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     try:
         from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        blas = [p for p in threadpool_info() if p.get("user_api") == "blas"]
+        if blas:
+            b = blas[0]
+            info["blas"] = {"library": b.get("internal_api"), "version": b.get("version"),
+                            "threads": b.get("num_threads"), "arch": b.get("architecture"),
+                            "file": os.path.basename(b.get("filepath", ""))}
     except Exception:
-        threads = os.cpu_count() or 1
+        pass
+    return info
+
+
+def _oracle_rate(tensors, seed, n_samples, threads=None):
+    """site-samples/s of the FP64 oracle on samples 0 .. n_samples-1 of a chain
+    (window with an open right end), with the BLAS thread count limited to
+    `threads` (None: as configured)."""
+    import oracle
+    from threadpoolctl import threadpool_limits, threadpool_info
+    with threadpool_limits(limits=threads, user_api="blas"):
+        used = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("user_api") == "blas"] or [1])
+        t0 = time.perf_counter()
+        oracle.sample(tensors, seed=seed, N=n_samples)
+        dt = time.perf_counter() - t0
+    return n_samples * len(tensors) / dt, dt, int(used)
+
+
+def cpu_baseline(t128, seed, n_samples, n_sites, n_samples_1t):
+    """The FP64 oracle as it stands, timed on the host cores.
+
+    value: all BLAS threads, samples 0 .. n_samples-1 (global indices) over
+    the first n_sites sites of the benchmarked chain (the 5 ramp sites and
+    the plateau after them).  Beside it: the same sites single-threaded on
+    n_samples_1t samples, and the small parity chain (M = 32, d = 4,
+    chi = 32, N = 4096) in full at both thread counts."""
+    import numpy  # noqa: F401  (loads the BLAS that threadpoolctl reports)
+    from paper_2512_20064_amd import synth
+    hi = host_info()
     window = t128[:n_sites]
-    t0 = time.perf_counter()
-    oracle.sample(window, seed=seed, N=n_samples)
-    dt = time.perf_counter() - t0
-    return {"value": n_samples * n_sites / dt, "unit": "site-samples/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"{n_samples} samples x first {n_sites} sites of the same chain, numpy FP64, {dt:.1f}s"}
+    v, dt, used = _oracle_rate(window, seed, n_samples)
+    v1, dt1, _ = _oracle_rate(window, seed, n_samples_1t, threads=1)
+    small = synth.small_chain(1, M=32, d=4, chi_max=32)[0]
+    vs, dts, _ = _oracle_rate(small, 1001, 4096)
+    vs1, dts1, _ = _oracle_rate(small, 1001, 4096, threads=1)
+    return {"value": v, "unit": "site-samples/s", "cores": used, "kind": "oracle",
+            "sample": (f"global samples 0..{n_samples - 1} x first {n_sites} sites of the benchmarked chain "
+                       f"(ramp 1,4,16,64,256 then chi=1024 plateau), numpy FP64 with {used} BLAS threads, "
+                       f"{dt:.1f}s"),
+            "single_thread": {"value": v1, "unit": "site-samples/s", "cores": 1,
+                              "sample": f"global samples 0..{n_samples_1t - 1} x the same {n_sites} sites, "
+                                        f"{dt1:.1f}s"},
+            "small_chain_full": {"workload": "M=32 d=4 chi=32 N=4096 (whole job)", "unit": "site-samples/s",
+                                 "value": vs, "cores": used, "seconds": round(dts, 2),
+                                 "single_thread_value": vs1, "single_thread_seconds": round(dts1, 2)},
+            "host": hi}
 
 
 def roofline_of(form, c_fl, c_n, c_ms, dt, m_ms, p_ms, chunk, products=None):
@@ -282,7 +332,7 @@ def run_chain_bench(args):
     cpu = None
     if not args.no_cpu_baseline and t128 is not None:
         log("timing the FP64 oracle on the host")
-        cpu = cpu_baseline(t128, seed, args.cpu_samples, min(args.cpu_sites, M))
+        cpu = cpu_baseline(t128, seed, args.cpu_samples, min(args.cpu_sites, M), args.cpu_samples_1t)
 
     metric = METRIC if args.workload == "resident" else f"site-samples/s, {args.workload} chain"
     rec = {
@@ -491,8 +541,9 @@ def main():
     ap.add_argument("--beside", default=None, help="comma-separated forms also timed ('' for none)")
     ap.add_argument("--beside-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-samples", type=int, default=1024)
-    ap.add_argument("--cpu-sites", type=int, default=512)
+    ap.add_argument("--cpu-samples", type=int, default=4096, help="oracle samples, all BLAS threads")
+    ap.add_argument("--cpu-samples-1t", type=int, default=256, help="oracle samples, one BLAS thread")
+    ap.add_argument("--cpu-sites", type=int, default=128, help="first sites of the chain the oracle takes")
     ap.add_argument("--no-profile", action="store_true", help="do not event-time each launch")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of this many MiB (reference for HBM counters)")

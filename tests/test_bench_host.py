@@ -57,3 +57,19 @@ def test_small_bond_roofline():
     assert r["achieved"] == pytest.approx(10.0) and r["peak"] == 157.3
     assert r["kernel"] == "sweep_small_kernel" and r["avg_launch_ms"] == pytest.approx(100.0)
     assert r["time_share"]["sweep_small"] == pytest.approx(0.3)
+
+
+def test_cpu_baseline_reports_threads_host_and_single_thread_leg():
+    """The oracle baseline names the host (nproc, CPU model, BLAS library),
+    times an all-threads and a one-thread leg, and the small chain in full."""
+    from paper_2512_20064_amd import synth
+    t, _, _ = synth.small_chain(2, M=8, d=2, chi_max=8)
+    r = bench.cpu_baseline(t, 5, 64, 6, 16)
+    assert r["kind"] == "oracle" and r["unit"] == "site-samples/s" and r["value"] > 0
+    assert r["cores"] >= 1 and r["single_thread"]["cores"] == 1 and r["single_thread"]["value"] > 0
+    assert "0..63" in r["sample"] and "6 sites" in r["sample"]
+    h = r["host"]
+    assert h["nproc"] >= 1 and h["affinity"] >= 1
+    assert h["blas"] is None or h["blas"]["library"]
+    s = r["small_chain_full"]
+    assert s["value"] > 0 and s["single_thread_value"] > 0 and "N=4096" in s["workload"]
