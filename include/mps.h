@@ -230,6 +230,34 @@ int mps_sample(mps_handle h, const void* const* tensors, int32_t dtype,
                int32_t* outcomes, double* logp);
 
 /*
+ * mps_sample without any device allocation, for callers that cannot allocate
+ * device memory: code under HIP stream capture, tight serving loops, and
+ * harnesses that forbid hipMalloc.  Arguments, results, status codes and
+ * bits are those of mps_sample with the same handle options.
+ *
+ * Scratch: instead of the handle's allocations, every call works in one
+ * fixed device array of MPS_NOALLOC_SCRATCH_BYTES (256 MiB) that the library
+ * holds on each device it runs on until the process ends.  The chunk size is
+ * reduced until a chunk's scratch fits in it (and under max_device_bytes, if
+ * set); when even one sample does not fit (e.g. a 16-bit form at a bond of
+ * several thousand, whose packed site tensor alone exceeds the array) the
+ * call returns MPS_ENOMEM naming the limit, before any HIP call.  The call
+ * makes no hipMalloc, hipFree, stream, event or graph creation: site tensors
+ * must be device-resident MPS_C64 (other storage is rejected with
+ * MPS_EINVAL), and the options profile and graph are ignored.
+ *
+ * Every call on a device shares that device's array, and the array keeps
+ * the last call's contents (each call initialises what it reads).  Calls
+ * that overlap on one device -- from two threads, or on two streams --
+ * race on the array and give undefined results; serialise them.
+ */
+#define MPS_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int mps_sample_noalloc(mps_handle h, const void* const* tensors, int32_t dtype,
+                       const int32_t* chi, const int32_t* d, int32_t M,
+                       int64_t N, int64_t n_offset, uint64_t seed,
+                       int32_t* outcomes, double* logp);
+
+/*
  * Draw N samples (global indices n_offset .. n_offset+N-1) from each of B
  * independent chains in one sweep: at every site index k, one contraction,
  * one measurement (and, for 16-bit forms, one packing) launch advance all

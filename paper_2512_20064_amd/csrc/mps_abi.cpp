@@ -39,6 +39,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -58,6 +59,37 @@ int fail(int code, const char* fmt, ...) {
 
 int hip_fail(hipError_t e, const char* what) {
   return fail(MPS_EHIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+// Fixed device scratch of mps_sample_noalloc: a file-scope device array, so
+// that the entry point needs no hipMalloc.  Every device the library runs on
+// holds its own copy (allocated when the code object is loaded) until the
+// process ends.  In host code `scratch` names a host-side stand-in, not the
+// device array: its device address is looked up once per device with
+// hipGetSymbolAddress (noalloc_scratch below) and only that address is used.
+constexpr size_t kNoAllocBytes = size_t(256) << 20;
+__device__ __align__(256) char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current).
+int noalloc_scratch(int device, void** ptr) {
+  if (device >= kMaxDevices) return fail(MPS_ENODEV, "mps_sample_noalloc: device %d >= %d", device, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(MPS_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s (%d)", device, hipGetErrorString(e),
+                  (int)e);
+    }
+    g_noalloc_ptr[device] = p;
+  }
+  *ptr = g_noalloc_ptr[device];
+  return MPS_OK;
 }
 
 constexpr int kMaxD = 16;
@@ -303,9 +335,18 @@ class PtrClassifier {
   std::map<uintptr_t, Range> ranges_;
 };
 
+// noalloc: run in the fixed device array `scratch` (mps_sample_noalloc)
+// instead of the handle's allocations; no HIP allocation of any kind is made
+// (no profiling events, no graph, no staging).
 int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offset, uint64_t seed, bool single,
-              int kind) {
+              int kind, bool noalloc = false) {
   const mps_options& o = h->opt;
+  // Cap on the scratch: the caller's max_device_bytes, and for noalloc the
+  // size of the fixed array.
+  const int64_t cap = noalloc ? (o.max_device_bytes > 0 ? std::min<int64_t>(o.max_device_bytes, (int64_t)kNoAllocBytes)
+                                                        : (int64_t)kNoAllocBytes)
+                              : o.max_device_bytes;
+  const char* const cap_name = noalloc ? "the fixed scratch of mps_sample_noalloc" : "max_device_bytes";
   const bool lowp = o.precision != MPS_FP32;
   const bool split = is_split(o.precision);
   const int form = lowp ? lp_form(o.precision) : 0;
@@ -315,15 +356,15 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
 
   // A lower bound of the scratch (one sample, one state, no staging) is
   // checked before any HIP call.
-  if (o.max_device_bytes > 0) {
+  if (cap > 0) {
     size_t lb = 0;
     for (int b = 0; b < B; ++b) {
       ChainBufs cb;
       lb += chain_layout(1, chains[b].sh, o.precision, 1, lb, cb);
     }
-    if ((int64_t)lb > o.max_device_bytes)
-      return fail(MPS_ENOMEM, "scratch for one sample per chain (%zu B) exceeds max_device_bytes (%lld)", lb,
-                  (long long)o.max_device_bytes);
+    if ((int64_t)lb > cap)
+      return fail(MPS_ENOMEM, "scratch for one sample per chain (%zu B) exceeds %s (%lld B)", lb, cap_name,
+                  (long long)cap);
   }
 
   // ---- device ----
@@ -333,7 +374,13 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
   if (h->device >= ndev) return fail(MPS_ENODEV, "device %d not present (%d devices)", h->device, ndev);
   if ((e = hipSetDevice(h->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
   hipStream_t stream = (hipStream_t)o.stream;
-  if (h->scratch_device >= 0 && h->scratch_device != h->device) return fail(MPS_EINVAL, "handle moved device");
+  void* fixed = nullptr;
+  if (noalloc) {
+    const int rc0 = noalloc_scratch(h->device, &fixed);
+    if (rc0) return rc0;
+  } else if (h->scratch_device >= 0 && h->scratch_device != h->device) {
+    return fail(MPS_EINVAL, "handle moved device");
+  }
 
   // ---- where each site tensor lives; which sites are staged ----
   // A site is used in place when it is device-resident complex64.  A site in
@@ -375,6 +422,9 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
   }
   const bool any_host = comp_max > 0;
   const size_t stage_need = any_staged ? 2 * align_up(dec_max) + 2 * align_up(comp_max) : 0;
+  if (noalloc && any_staged)
+    return fail(MPS_EINVAL, "mps_sample_noalloc: every site tensor must be device-resident MPS_C64 (other forms "
+                "need staging buffers)");
 
   // Order of the sweep.  Without staged sites the chunks are the outer loop
   // and each chunk walks every site with one reused left-vector state.  With
@@ -438,15 +488,14 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
     }
     return off;
   };
-  if (o.max_device_bytes > 0) {
+  if (cap > 0) {
     // with one state per chunk, tiny chunks only multiply the tables
     const int64_t floor_rows = site_outer ? std::min<int64_t>(N, 1024) : 1;
-    while (nc > floor_rows && (int64_t)(scratch_for(nc, nullptr) + stage_need) > o.max_device_bytes)
+    while (nc > floor_rows && (int64_t)(scratch_for(nc, nullptr) + stage_need) > cap)
       nc = std::max<int64_t>(floor_rows, (nc + 1) / 2);
-    if ((int64_t)(scratch_for(nc, nullptr) + stage_need) > o.max_device_bytes)
+    if ((int64_t)(scratch_for(nc, nullptr) + stage_need) > cap)
       return fail(MPS_ENOMEM, "scratch for %lld-sample chunks (%zu B) plus site staging (%zu B) exceeds "
-                  "max_device_bytes (%lld)", (long long)nc, scratch_for(nc, nullptr), stage_need,
-                  (long long)o.max_device_bytes);
+                  "%s (%lld B)", (long long)nc, scratch_for(nc, nullptr), stage_need, cap_name, (long long)cap);
   }
   std::vector<ChainBufs> bufs(B);
   const size_t total = scratch_for(nc, &bufs);
@@ -471,10 +520,12 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
     have = need;
     return MPS_OK;
   };
-  int rc = grow(h->scratch, h->scratch_bytes, total, "sweep scratch");
-  if (rc) return rc;
-  h->scratch_device = h->device;
-  if ((rc = grow(h->stage, h->stage_bytes, stage_need, "site staging"))) return rc;
+  int rc = MPS_OK;
+  if (!noalloc) {
+    if ((rc = grow(h->scratch, h->scratch_bytes, total, "sweep scratch"))) return rc;
+    h->scratch_device = h->device;
+    if ((rc = grow(h->stage, h->stage_bytes, stage_need, "site staging"))) return rc;
+  }
   float2* dec_slot[2] = {nullptr, nullptr};
   void* comp_slot[2] = {nullptr, nullptr};
   if (any_staged) {
@@ -497,7 +548,7 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
     return (single && staged[k]) ? dec_slot[k & 1] : (const float2*)chains[b].tensors[k];
   };
 
-  char* const base = (char*)h->scratch;
+  char* const base = noalloc ? (char*)fixed : (char*)h->scratch;
   char* const dtab = base;                                  // problem tables
   int* const nflag = (int*)(base + align_up(table_bytes));  // flagged-sample counter
   auto at = [&](size_t off) -> void* { return base + off; };
@@ -633,8 +684,8 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
 
   // ---- launches ----
   const int group = o.tile_group > 0 ? o.tile_group : kDefaultGroup;
-  const bool prof = o.profile != 0;
-  const bool use_graph = o.graph != 0 && stream != nullptr && !prof && nchunks > 1 && !site_outer;
+  const bool prof = o.profile != 0 && !noalloc;
+  const bool use_graph = o.graph != 0 && stream != nullptr && !prof && nchunks > 1 && !site_outer && !noalloc;
   // Timing events per site: pack, contraction, measurement, copy, expansion
   // (begin, end); a pair is summed once its end has been recorded and waited.
   constexpr int EV = 10;
@@ -757,7 +808,7 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
 
   mps_stats st{};
   st.n_chunk = nc;
-  st.scratch_bytes = (int64_t)(h->scratch_bytes + h->stage_bytes);
+  st.scratch_bytes = noalloc ? (int64_t)total : (int64_t)(h->scratch_bytes + h->stage_bytes);
   auto count = [&](int k, int rows, bool pack) {
     const Step& sp = steps[k];
     st.pack_launches += (lowp && pack) ? 1 : 0;
@@ -974,6 +1025,22 @@ int mps_sample(mps_handle h, const void* const* tensors, int32_t dtype, const in
   }
   if (!outcomes) return fail(MPS_EINVAL, "outcomes is NULL");
   return run_sweep(h, chains, N, n_offset, seed, true, dtype);
+}
+
+int mps_sample_noalloc(mps_handle h, const void* const* tensors, int32_t dtype, const int32_t* chi, const int32_t* d,
+                       int32_t M, int64_t N, int64_t n_offset, uint64_t seed, int32_t* outcomes, double* logp) {
+  int rc = check_call(h, dtype, N, n_offset);
+  if (rc) return rc;
+  if (dtype != MPS_C64) return fail(MPS_EINVAL, "mps_sample_noalloc: dtype must be MPS_C64");
+  std::vector<Chain> chains(1);
+  chains[0] = Chain{tensors, chi, d, M, h->opt.mps_id, outcomes, logp, Shape{}};
+  if ((rc = validate_chain(chains[0], h->opt.precision, chains[0].sh, 0))) return rc;
+  if (N == 0) {
+    h->st = mps_stats{};
+    return MPS_OK;
+  }
+  if (!outcomes) return fail(MPS_EINVAL, "outcomes is NULL");
+  return run_sweep(h, chains, N, n_offset, seed, true, dtype, true);
 }
 
 int mps_sample_batch(mps_handle h, int32_t B, const mps_chain* chains_in, int32_t dtype, int64_t N,

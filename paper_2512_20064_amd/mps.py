@@ -24,8 +24,9 @@ STORAGE = {"c64": MPS_C64, "cf16": MPS_CF16, "cf8": MPS_CF8}
 STATUS_NAMES = {0: "MPS_OK", -1: "MPS_EINVAL", -2: "MPS_ENOMEM", -3: "MPS_ENODEV",
                 -4: "MPS_EHIP", -5: "MPS_ENUMERIC"}
 
-EXPORTS = ("mps_options_init", "mps_create", "mps_set_options", "mps_sample", "mps_sample_batch",
-           "mps_autotune", "mps_get_stats", "mps_last_error", "mps_destroy")
+EXPORTS = ("mps_options_init", "mps_create", "mps_set_options", "mps_sample", "mps_sample_noalloc",
+           "mps_sample_batch", "mps_autotune", "mps_get_stats", "mps_last_error", "mps_destroy")
+NOALLOC_SCRATCH_BYTES = 256 << 20
 
 
 def stored_bytes(kind: str, chi_l: int, d: int, chi_r: int) -> int:
@@ -147,6 +148,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_int64,
                                ctypes.c_int64, ctypes.c_uint64, P, P]
     lib.mps_sample.restype = ctypes.c_int
+    lib.mps_sample_noalloc.argtypes = lib.mps_sample.argtypes
+    lib.mps_sample_noalloc.restype = ctypes.c_int
     lib.mps_sample_batch.argtypes = [P, ctypes.c_int32, ctypes.POINTER(mps_chain), ctypes.c_int32, ctypes.c_int64,
                                      ctypes.c_int64, ctypes.c_uint64]
     lib.mps_sample_batch.restype = ctypes.c_int
@@ -201,6 +204,17 @@ def mps_sample(h, tensor_ptrs, dtype: int, chi, d, M: int, N: int, n_offset: int
     return load().mps_sample(h, arr, dtype, chi_a, d_a, M, N, n_offset, ctypes.c_uint64(seed),
                              ctypes.c_void_p(outcomes_ptr) if outcomes_ptr else None,
                              ctypes.c_void_p(logp_ptr) if logp_ptr else None)
+
+
+def mps_sample_noalloc(h, tensor_ptrs, dtype: int, chi, d, M: int, N: int, n_offset: int, seed: int,
+                       outcomes_ptr: int, logp_ptr: int | None) -> int:
+    """Raw call of the allocation-free variant; returns the status code."""
+    arr = (ctypes.c_void_p * len(tensor_ptrs))(*[ctypes.c_void_p(int(p)) if p else None for p in tensor_ptrs])
+    chi_a = (ctypes.c_int32 * len(chi))(*[int(x) for x in chi])
+    d_a = (ctypes.c_int32 * len(d))(*[int(x) for x in d])
+    return load().mps_sample_noalloc(h, arr, dtype, chi_a, d_a, M, N, n_offset, ctypes.c_uint64(seed),
+                                     ctypes.c_void_p(outcomes_ptr) if outcomes_ptr else None,
+                                     ctypes.c_void_p(logp_ptr) if logp_ptr else None)
 
 
 def mps_autotune(h, tensor_ptrs, dtype: int, chi, d, M: int, N: int, seed: int):

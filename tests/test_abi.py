@@ -180,3 +180,28 @@ def test_bonds_of_shapes_checks_the_chain():
         mps._bonds_of_shapes([(1, 2)])
     with pytest.raises(ValueError, match="no sites"):
         mps._bonds_of_shapes([])
+
+
+def test_noalloc_validates_on_host():
+    """mps_sample_noalloc checks its arguments like mps_sample, rejects stored
+    forms, and reports a chain whose single-sample scratch exceeds the fixed
+    array (a 16-bit form whose packed site tensor alone is gigabytes) as
+    MPS_ENOMEM before any HIP call."""
+    h = mps.mps_create(0)
+    try:
+        def call(**kw):
+            a = dict(tensors=[1, 1], dtype=mps.MPS_C64, chi=[1, 4, 1], d=[4, 4], M=2, N=10)
+            a.update(kw)
+            return mps.mps_sample_noalloc(h, a["tensors"], a["dtype"], a["chi"], a["d"], a["M"], a["N"], 0, 1, 1, 0)
+        assert call(chi=[2, 4, 1]) == mps.MPS_EINVAL
+        assert call(dtype=mps.MPS_CF16) == mps.MPS_EINVAL
+        assert call(N=0) == mps.MPS_OK
+        o = mps.mps_options_init()
+        o.precision = mps.MPS_BF16X3
+        mps.mps_set_options(h, o)
+        chi = [1, 16, 256, 4096, 65536, 4096, 256, 16, 1]
+        rc = call(tensors=[1] * 8, chi=chi, d=[16] * 8, M=8)
+        assert rc == mps.MPS_ENOMEM, (rc, mps.mps_last_error())
+        assert "mps_sample_noalloc" in mps.mps_last_error()
+    finally:
+        mps.mps_destroy(h)
