@@ -55,6 +55,10 @@ FORMS = {
              "dtype": "f16"},
     "fp16x3": {"peak": 2516.6, "mfma_per_alg": 3, "kernel": "contract_lp_kernel<f16,3>", "src": "contract_lp.hip",
                "dtype": "f16x3"},
+    # one fp16 product plus two FP8 products at twice the fp16 rate: two
+    # fp16-product equivalents of MFMA time per complex product
+    "fp16f8": {"peak": 2516.6, "mfma_per_alg": 2, "kernel": "contract_f16f8_kernel", "src": "contract_lp.hip",
+               "dtype": "f16+f8"},
 }
 
 

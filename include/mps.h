@@ -63,10 +63,23 @@ enum {
                         d = 4 chain the error against an FP64 evaluation reaches
                         3.3e-3 within 32 sites.  Kept as a measured speed/accuracy
                         point; use MPS_BF16X3 or MPS_FP16X3 for the 1e-3 bar.      */
-  MPS_FP16X3 = 3     /* split precision in fp16: x = hi + lo (fp16 each), three
+  MPS_FP16X3 = 3,    /* split precision in fp16: x = hi + lo (fp16 each), three
                         products as MPS_BF16X3 on v_mfma_f32_32x32x16_f16; 11-bit
                         parts (22 bits together) but a narrower exponent range:
                         lo parts below 2^-24 flush to zero                        */
+  MPS_FP16F8 = 4     /* split precision with FP8 corrections: W = Lh*Ah in fp16 on
+                        v_mfma_f32_32x32x16_f16 plus the two correction products
+                        Lh*Al + Ll*Ah in OCP FP8 E4M3 on the block-scaled
+                        v_mfma_scale_f32_32x32x64_f8f6f4 (one FP8 instruction per
+                        32 real K takes both corrections).  Each complex column of
+                        a site tensor is divided by a power of two that brings its
+                        largest |re|, |im| to at most 448 (multiplied back after the
+                        product, exactly); the FP8 operands carry fixed powers of
+                        two (left vector: 2^8 on Lh, 2^19 on Ll; site: 2^11 on Al)
+                        and the products a common 2^-19 E8M0 scale.  The
+                        corrections need only a few significant bits each: two
+                        fp16-product equivalents of MFMA time per complex product
+                        instead of three.                                         */
 };
 
 /* Storage of the site tensors (Section 3.3.2: tensors stored and moved in
@@ -108,7 +121,7 @@ enum {
 typedef struct mps_ctx* mps_handle;
 
 typedef struct {
-  int32_t precision;        /* MPS_FP32, MPS_BF16X3, MPS_FP16 or MPS_FP16X3       */
+  int32_t precision;        /* MPS_FP32, MPS_BF16X3, MPS_FP16, MPS_FP16X3, MPS_FP16F8 */
   int32_t profile;          /* 1: time every kernel launch with HIP events        */
   int64_t n_chunk;          /* samples per pass over the chain; 0 = planner picks */
   int64_t max_device_bytes; /* cap on scratch bytes; 0 = no cap                  */

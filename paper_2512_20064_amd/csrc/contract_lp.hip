@@ -10,6 +10,14 @@
 //   fp16    one product on v_mfma_f32_32x32x16_f16 with the left vector
 //           renormalised per sample (|l_i| <= 1) and the site tensor's
 //           entries bounded by 1 (orthonormal rows).
+//   fp16f8  the fp16 product of the high parts, plus the two correction
+//           products Lh*Bl and Ll*Bh in OCP FP8 E4M3 on the block-scaled
+//           v_mfma_scale_f32_32x32x64_f8f6f4 (operand formats and scales in
+//           sweep.h, kFp16F8).  One FP8 instruction takes 64 K values per
+//           row and column: 32 real K values of each correction product,
+//           so per 32 real K a 32x32 block costs two fp16 MFMAs (32 cycles
+//           each) and one FP8 MFMA (64 cycles), against six 16-bit MFMAs
+//           for bf16x3.
 //
 // Complex arithmetic uses the real embedding of the site tensor: real column
 // (c, p) of branch i multiplies the interleaved left vector (re, im) by
@@ -318,6 +326,339 @@ __global__ __launch_bounds__(NTHR, 1) void contract_lp_kernel(const ContractLpPr
   }
 }
 
+// ------------------------------------------------------------ fp16f8 ----
+
+typedef int intx4 __attribute__((ext_vector_type(4)));
+typedef int intx8 __attribute__((ext_vector_type(8)));
+
+// E8M0 scale codes of the FP8 products: 2^-19 on the left-vector operand
+// (the common factor of both corrections), 2^0 on the site tensor's.
+constexpr int kScale8L = 127 - 19;
+constexpr int kScale8B = 127;
+
+// Smallest power of two s with amax / s <= 448 (the largest finite E4M3
+// value), exponent clamped to the normal FP32 range; 1 for zero or a
+// non-finite amax (which then shows as a non-finite S downstream).
+__device__ inline float pow2_scale(float amax) {
+  if (!(amax > 0.f) || isinf(amax)) return 1.f;
+  int E;
+  const float m = frexpf(amax, &E);  // amax = m * 2^E, m in [0.5, 1); 448 = 0.875 * 2^9
+  int e = m <= 0.875f ? E - 9 : E - 8;
+  e = e < -126 ? -126 : e;
+  return ldexpf(1.f, e);
+}
+
+// Four floats to four E4M3 codes (round to nearest even), first in the low byte.
+__device__ inline unsigned e4m3x4(float a, float b, float c, float d) {
+  int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+  w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+  return (unsigned)w;
+}
+
+// Column scales: one workgroup per 64 complex columns of one branch; 4 row
+// phases of 64 threads, maximum of |re| and |im| over the column.
+__global__ __launch_bounds__(256) void colscale_kernel(const PackProb* probs, const int* cm_start, int nprob) {
+  __shared__ float part[4][64];
+  const int p = find_problem(cm_start, nprob, blockIdx.x);
+  const PackProb a = probs[p];
+  const int wb = blockIdx.x - cm_start[p];
+  const int ncb = a.CP / 64;
+  const int br = wb / ncb;
+  const int c = (wb - br * ncb) * 64 + (threadIdx.x & 63);
+  const int ph = threadIdx.x >> 6;
+  float m = 0.f;
+  if (c < a.chi_r) {
+    const size_t pitch = (size_t)a.d * a.chi_r;
+    const float2* col = a.A + (size_t)br * a.chi_r + c;
+    for (int l = ph; l < a.K; l += 4) {
+      const float2 z = col[(size_t)l * pitch];
+      m = fmaxf(m, fmaxf(fabsf(z.x), fabsf(z.y)));
+    }
+  }
+  part[ph][threadIdx.x & 63] = m;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const float mm = fmaxf(fmaxf(part[0][threadIdx.x], part[1][threadIdx.x]),
+                           fmaxf(part[2][threadIdx.x], part[3][threadIdx.x]));
+    a.colscale[(size_t)br * a.CP + c] = pow2_scale(mm);
+  }
+}
+
+// Packing of the fp16f8 operands: the same tiles as pack_kernel; each real
+// value v (column already divided by its scale) gives h = fp16(v) into the
+// 16-bit plane and the codes e4m3(h), e4m3((v - h) * 2^11) into the pair
+// plane (low part first: [B8l | B8h]).
+__global__ __launch_bounds__(256) void pack_f16f8_kernel(const PackProb* probs, const int* blk_start, int nprob) {
+  __shared__ float2 tile[PK_L][PK_P];
+  const int p = find_problem(blk_start, nprob, blockIdx.x);
+  const PackProb a = probs[p];
+  const int lb = blockIdx.x - blk_start[p];
+  const int ncb = a.CP / PK_C, nlb = a.Kp / (2 * PK_L);
+  const int c0 = (lb % ncb) * PK_C;
+  const int l0 = ((lb / ncb) % nlb) * PK_L;
+  const int br = lb / (ncb * nlb);
+  const int tid = threadIdx.x;
+  const size_t pitch = (size_t)a.d * a.chi_r;
+#pragma unroll
+  for (int it = 0; it < PK_L * PK_C / 256; ++it) {
+    const int idx = it * 256 + tid;
+    const int l = idx / PK_C, c = idx % PK_C;
+    const int gl = l0 + l, gc = c0 + c;
+    tile[l][c] = (gl < a.K && gc < a.chi_r) ? a.A[(size_t)gl * pitch + (size_t)br * a.chi_r + gc]
+                                            : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  f16_t* Bh = (f16_t*)a.Bh;
+  unsigned char* B8 = (unsigned char*)a.Bl;
+#pragma unroll
+  for (int it = 0; it < 2 * PK_C * 8 / 256; ++it) {
+    const int idx = it * 256 + tid;
+    const int rowl = idx >> 3, ch = idx & 7;
+    const int c = rowl >> 1, p = rowl & 1;
+    const float inv = 1.f / a.colscale[(size_t)br * a.CP + c0 + c];  // exact: a power of two
+    float v[8];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const float2 z = tile[ch * 4 + m][c];
+      v[2 * m] = (p ? z.y : z.x) * inv;
+      v[2 * m + 1] = (p ? z.x : -z.y) * inv;
+    }
+    f16x8 h;
+    float hf[8], lo[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      h[e] = (f16_t)v[e];
+      hf[e] = (float)h[e];
+      lo[e] = (v[e] - hf[e]) * 2048.f;
+    }
+    const size_t orow = ((size_t)br * a.CP + c0 + c) * 2 + p;
+    const int k = 2 * l0 + ch * 8;
+    *reinterpret_cast<f16x8*>(Bh + kblk_off(orow, k, a.Kp)) = h;
+    unsigned char* d8 = B8 + pair_off(orow, k, a.Kp);
+    *reinterpret_cast<uint2*>(d8) = make_uint2(e4m3x4(lo[0], lo[1], lo[2], lo[3]), e4m3x4(lo[4], lo[5], lo[6], lo[7]));
+    *reinterpret_cast<uint2*>(d8 + 16) =
+        make_uint2(e4m3x4(hf[0], hf[1], hf[2], hf[3]), e4m3x4(hf[4], hf[5], hf[6], hf[7]));
+  }
+}
+
+// The fp16f8 contraction.  Same tile (256 x 256 real), waves, operand
+// loading (global_load_lds into a 5-slice LDS ring) and epilogue as
+// contract_lp_kernel; a slice holds 16 real K of [Lh | L8 | Bh | B8].  The FP8
+// instruction takes 32 bytes per lane: lane half h of a row (column) reads
+// its 32-byte row of the pair plane from slice 2m + h, so one instruction
+// covers the slice pair (2m, 2m+1) and both correction products on it.  The
+// slices are made readable a pair at a time (one barrier per 32 real K):
+// while pair m is read and multiplied, slices 2m+2 .. 2m+4 are in flight,
+// and the loads issued after the barrier of pair m+1 (slices 2m+5, 2m+6)
+// refill the two buffers of pair m, whose LDS reads every wave has finished
+// (LDS-read wait before the barrier).
+__global__ __launch_bounds__(NTHR, 1) void contract_f16f8_kernel(const ContractLpProb* probs, const int* tn_start,
+                                                                 int nprob, int tn_total, int tiles_m, int per_xcd,
+                                                                 int group_m, const ChunkArgs* chp) {
+  constexpr int NARR = 4;  // Lh, L8 (pair plane), Bh, B8 (pair plane)
+  constexpr int STAGE = NARR * ARR;
+  constexpr int IPW = NARR;
+  __shared__ __attribute__((aligned(16))) char lds[NST * STAGE];
+
+  int tm, tng;
+  if (!map_tile(blockIdx.x, tiles_m, tn_total, per_xcd, group_m, tm, tng)) return;
+  const int rows = chp->rows;
+  const int p = find_problem(tn_start, nprob, tng);
+  const ContractLpProb a = probs[p];
+  const int tn = tng - tn_start[p];
+  const int T_ = a.CP / kLpBNC;
+  const int branch = tn / T_;
+  const int ct = tn - branch * T_;
+  const int m0 = tm * BM;
+  const int c0 = ct * kLpBNC;
+  const size_t cblk = ((size_t)branch * a.CP + c0) * 2 / BM;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = (wave >> 1) * 64;
+  const int wc = (wave & 1) * 128;
+  const int half = lane >> 5;
+  const int j = lane & 31;
+
+  // Loads: planes and pair planes are addressed alike (8 KiB per 256 rows
+  // and 16 K).  Load i of a wave reads array q = (wave*IPW + i) / 8, a choice
+  // that is uniform over the wave, through a buffer descriptor (scalar
+  // registers) based at the tile's 256-row block; the slice is a scalar
+  // offset and each lane keeps one 32-bit byte offset.
+  const size_t kbs = (size_t)(a.Kp / BK) * 8192;  // bytes per 256-row block
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  __amdgpu_buffer_rsrc_t rsrc[IPW];
+  int voff[IPW], ldst[IPW];
+#pragma unroll
+  for (int i = 0; i < IPW; ++i) {
+    const int idx = wv * IPW + i;
+    const int q = idx >> 3, rg = idx & 7;  // q: 0 Lh, 1 L8, 2 Bh, 3 B8
+    const char* base = q == 0 ? (const char*)a.Lh + (size_t)tm * kbs
+                     : q == 1 ? (const char*)a.Ll + (size_t)tm * kbs
+                     : q == 2 ? (const char*)a.Bh + cblk * kbs
+                              : (const char*)a.Bl + cblk * kbs;
+    rsrc[i] = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)0xFFFFFFFF, 0x00020000);
+    const int row = rg * 32 + (lane >> 1);
+    const int lc = (lane & 1) ^ swz(row);
+    voff[i] = row * 32 + lc * 16;
+    ldst[i] = q * ARR + rg * 1024;
+  }
+  auto issue = [&](int kt) {
+    char* st = lds + (kt % NST) * STAGE;
+#pragma unroll
+    for (int i = 0; i < IPW; ++i)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc[i], (__attribute__((address_space(3))) void*)(st + ldst[i]), 16,
+                                               voff[i], kt * 8192, 0, 0);
+  };
+
+  floatx16 acc[2][4];
+  const floatx16 zero = {};
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = zero;
+
+  struct Ops16 {
+    f16x8 a[2], b[4];
+  };
+  struct Ops8 {
+    intx8 a[2], b[4];
+  };
+  // LDS read offsets.  Rows r and r + 32 have the same swizzle (it depends
+  // on row bits 2 and 3 only), so one offset per operand and chunk serves
+  // every row block, the blocks being 1 KiB apart (immediate offsets).
+  const int sj = swz(j);
+  const unsigned a_h = (unsigned)((wr + j) * 32 + ((half ^ sj) << 4));           // Lh, chunk `half`
+  const unsigned b_h = (unsigned)(2 * ARR + (wc + j) * 32 + ((half ^ sj) << 4));  // Bh, chunk `half`
+  const unsigned a8_0 = (unsigned)(ARR + (wr + j) * 32 + (sj << 4));              // L8, chunk 0
+  const unsigned a8_1 = (unsigned)(ARR + (wr + j) * 32 + ((1 ^ sj) << 4));        // L8, chunk 1
+  const unsigned b8_0 = (unsigned)(3 * ARR + (wc + j) * 32 + (sj << 4));          // B8, chunk 0
+  const unsigned b8_1 = (unsigned)(3 * ARR + (wc + j) * 32 + ((1 ^ sj) << 4));    // B8, chunk 1
+  auto read16 = [&](int kt, Ops16& o) {
+    const char* st = lds + (kt % NST) * STAGE;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) o.a[rb] = *reinterpret_cast<const f16x8*>(st + a_h + rb * 1024);
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) o.b[cb] = *reinterpret_cast<const f16x8*>(st + b_h + cb * 1024);
+  };
+  auto cat = [](intx4 x, intx4 y) -> intx8 { return __builtin_shufflevector(x, y, 0, 1, 2, 3, 4, 5, 6, 7); };
+  auto read8 = [&](int m, Ops8& o) {
+    const char* st = lds + ((2 * m + half) % NST) * STAGE;  // lane half h: slice 2m + h
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+      o.a[rb] = cat(*reinterpret_cast<const intx4*>(st + a8_0 + rb * 1024),
+                    *reinterpret_cast<const intx4*>(st + a8_1 + rb * 1024));
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+      o.b[cb] = cat(*reinterpret_cast<const intx4*>(st + b8_0 + cb * 1024),
+                    *reinterpret_cast<const intx4*>(st + b8_1 + cb * 1024));
+  };
+  auto mma16 = [&](const Ops16& o) {
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(o.a[rb], o.b[cb], acc[rb][cb], 0, 0, 0);
+  };
+  auto mma8 = [&](const Ops8& o) {
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+        acc[rb][cb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(o.a[rb], o.b[cb], acc[rb][cb], 0, 0, 0, kScale8L,
+                                                                      0, kScale8B);
+  };
+
+  const int nkt = a.Kp / BK;  // a multiple of 4
+  const int npair = nkt >> 1;
+  int issued = 0;
+  // Pair m readable: slices 2m and 2m+1 landed (slice 2m+2, issued after
+  // them, may stay in flight), this wave's LDS reads done, one barrier; then
+  // the next two slices are issued into the buffers of pair m-1.
+  auto open_pair = [&](int m) {
+    if (issued > 2 * m + 2) __builtin_amdgcn_s_waitcnt(vmcnt_lgkm0_imm(IPW));
+    else __builtin_amdgcn_s_waitcnt(vmcnt_lgkm0_imm(0));
+    asm volatile("s_barrier" ::: "memory");
+    if (issued < nkt) issue(issued++);
+    if (issued < nkt) issue(issued++);
+  };
+#pragma unroll
+  for (int i = 0; i < 3; ++i) issue(issued++);
+  // Operand registers: e (even slice, fp16), h (odd slice, fp16), f (FP8
+  // operands of the pair); at most two of them are live at a time, each
+  // read while the MFMAs of another run.
+  Ops16 e, h;
+  Ops8 f;
+  open_pair(0);
+  read16(0, e);
+  read8(0, f);
+  // (sched_barrier: the compiler keeps this order instead of hoisting the
+  // next reads above the MFMAs, which would need a third register set)
+  for (int m = 0; m < npair; ++m) {
+    mma16(e);
+    __builtin_amdgcn_sched_barrier(0);
+    read16(2 * m + 1, h);
+    mma8(f);
+    __builtin_amdgcn_sched_barrier(0);
+    if (m + 1 < npair) {
+      open_pair(m + 1);
+      read16(2 * m + 2, e);
+    }
+    mma16(h);
+    __builtin_amdgcn_sched_barrier(0);
+    if (m + 1 < npair) read8(m + 1, f);
+  }
+  __syncthreads();  // the stage buffers are reused below
+
+  // Column scales: W[:, c] = s_c * acc (exact, a power of two).
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    const float sc = a.colscale[(size_t)branch * a.CP + c0 + ((wc + cb * 32 + j) >> 1)];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[rb][cb][v] *= sc;
+  }
+
+  const int ncols = a.d * a.chi_r;
+  float* Wf = reinterpret_cast<float*>(a.W);
+  const size_t wpitch = 2 * (size_t)ncols;
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb) {
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      const int rc = wc + cb * 32 + j;
+      const int colc = c0 + (rc >> 1);
+      const size_t fcol = 2 * ((size_t)branch * a.chi_r + c0) + rc;
+      if (colc < a.chi_r) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int gr = m0 + wr + rb * 32 + (v >> 2) * 8 + half * 4 + (v & 3);
+          if (gr < rows) Wf[(size_t)gr * wpitch + fcol] = acc[rb][cb][v];
+        }
+      }
+    }
+  }
+  float* red = reinterpret_cast<float*>(lds);
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      float s2 = 0.f;
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) s2 += acc[rb][cb][v] * acc[rb][cb][v];
+#pragma unroll
+      for (int off = 16; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 32);
+      if (j == 0) red[(wave & 1) * BM + wr + rb * 32 + (v >> 2) * 8 + half * 4 + (v & 3)] = s2;
+    }
+  }
+  __syncthreads();
+  if (tid < BM) {
+    const int gr = m0 + tid;
+    if (gr < rows) a.qpart[(size_t)gr * (a.d * T_) + branch * T_ + ct] = red[tid] + red[BM + tid];
+  }
+}
+
 template <typename T, int NPROD>
 hipError_t launch_pack_t(const PackProb* probs, const int* blk_start, int nprob, int blk_total, hipStream_t s) {
   if (nprob <= 0 || blk_total <= 0) return hipSuccess;
@@ -339,8 +680,19 @@ hipError_t launch_contract_t(const ContractLpProb* probs, const int* tn_start, i
 
 }  // namespace
 
+hipError_t launch_colscale(const PackProb* probs, const int* cm_start, int nprob, int cm_total, hipStream_t s) {
+  if (nprob <= 0 || cm_total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(colscale_kernel, dim3(cm_total), dim3(256), 0, s, probs, cm_start, nprob);
+  return hipGetLastError();
+}
+
 hipError_t launch_pack_lp(int form, const PackProb* probs, const int* blk_start, int nprob, int blk_total,
                           hipStream_t s) {
+  if (form == kFp16F8) {
+    if (nprob <= 0 || blk_total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pack_f16f8_kernel, dim3(blk_total), dim3(256), 0, s, probs, blk_start, nprob);
+    return hipGetLastError();
+  }
   if (form == kBf16x3) return launch_pack_t<bf16_t, 3>(probs, blk_start, nprob, blk_total, s);
   if (form == kFp16x3) return launch_pack_t<f16_t, 3>(probs, blk_start, nprob, blk_total, s);
   return launch_pack_t<f16_t, 1>(probs, blk_start, nprob, blk_total, s);  // kFp16, kFp16x2: high parts only
@@ -348,6 +700,15 @@ hipError_t launch_pack_lp(int form, const PackProb* probs, const int* blk_start,
 
 hipError_t launch_contract_lp(int form, const ContractLpProb* probs, const int* tn_start, int nprob, int tn_total,
                               const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s) {
+  if (form == kFp16F8) {
+    const int tiles_m = (grid_rows + BM - 1) / BM;
+    const long long ntiles = (long long)tiles_m * tn_total;
+    if (ntiles <= 0 || nprob <= 0) return hipSuccess;
+    const int per_xcd = (int)((ntiles + 7) / 8);
+    hipLaunchKernelGGL(contract_f16f8_kernel, dim3(per_xcd * 8), dim3(NTHR), 0, s, probs, tn_start, nprob, tn_total,
+                       tiles_m, per_xcd, group_m, ch);
+    return hipGetLastError();
+  }
   if (form == kBf16x3)
     return launch_contract_t<bf16_t, 3>(probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s);
   if (form == kFp16x3)

@@ -44,7 +44,7 @@ typedef _Float16 f16_t;
 
 constexpr int DMAX = 16;
 
-enum Out { kOutF32 = 0, kOutBf16x2 = 1, kOutF16 = 2, kOutF16x2 = 3 };
+enum Out { kOutF32 = 0, kOutBf16x2 = 1, kOutF16 = 2, kOutF16x2 = 3, kOutF16F8 = 4 };
 
 // Left-vector writers for the three operand formats.
 template <int OUT>
@@ -160,6 +160,71 @@ struct LWriter<kOutF16> {
   __device__ void pad_from(int k0, int sl, int W) {
     for (int k = k0 + 8 * sl; k < ld; k += 8 * W)
       *reinterpret_cast<uint4*>(hi + (kblk_off(row, k, ld) >> 1)) = make_uint4(0u, 0u, 0u, 0u);
+  }
+};
+
+// fp16f8 writer: the fp16 plane Lh = fp16(x), and the pair plane of E4M3
+// codes e4m3(Lh * 2^8) (bytes 0..15 of a row's 16-K slice) and
+// e4m3((x - Lh) * 2^19) (bytes 16..31).  |x| <= 1 after renormalisation, so
+// both codes are finite (at most 256 and 128).
+template <>
+struct LWriter<kOutF16F8> {
+  uint32_t* hi;
+  unsigned char* p8;
+  size_t row;
+  int ld;
+  __device__ LWriter(const MeasureProb& a, int r)
+      : hi((uint32_t*)a.Lh), p8((unsigned char*)a.Ll), row((size_t)r), ld(a.ld_out) {}
+  static __device__ uint32_t pack2(f16_t a, f16_t b) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+  }
+  // two values -> two codes of the high part and two of the low part
+  static __device__ void codes2(float x, float y, f16_t& xh, f16_t& yh, unsigned& c_hi, unsigned& c_lo) {
+    xh = (f16_t)x;
+    yh = (f16_t)y;
+    const float xf = (float)xh, yf = (float)yh;
+    c_hi = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(xf * 256.f, yf * 256.f, 0, false) & 0xFFFFu;
+    c_lo = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32((x - xf) * 524288.f, (y - yf) * 524288.f, 0, false) & 0xFFFFu;
+  }
+  __device__ void put(int r, float x, float y) {
+    f16_t xh, yh;
+    unsigned ch, cl;
+    codes2(x, y, xh, yh, ch, cl);
+    hi[kblk_off(row, 2 * r, ld) >> 1] = pack2(xh, yh);
+    const size_t o = pair_off(row, 2 * r, ld);
+    *reinterpret_cast<uint16_t*>(p8 + o) = (uint16_t)ch;
+    *reinterpret_cast<uint16_t*>(p8 + o + 16) = (uint16_t)cl;
+  }
+  // complex r4 .. r4+3: K values 2*r4 .. 2*r4+7, half of a 16-K slice
+  __device__ void put4(int r4, const float2 (&v)[4]) {
+    uint32_t h[4];
+    unsigned ch[4], cl[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      f16_t xh, yh;
+      codes2(v[j].x, v[j].y, xh, yh, ch[j], cl[j]);
+      h[j] = pack2(xh, yh);
+    }
+    *reinterpret_cast<uint4*>(hi + (kblk_off(row, 2 * r4, ld) >> 1)) = make_uint4(h[0], h[1], h[2], h[3]);
+    const size_t o = pair_off(row, 2 * r4, ld);
+    *reinterpret_cast<uint2*>(p8 + o) = make_uint2(ch[0] | (ch[1] << 16), ch[2] | (ch[3] << 16));
+    *reinterpret_cast<uint2*>(p8 + o + 16) = make_uint2(cl[0] | (cl[1] << 16), cl[2] | (cl[3] << 16));
+  }
+  __device__ void pad(const MeasureProb& a, int sl, int W) {
+    for (int k = 2 * a.chi_r + 2 * sl; k < ld; k += 2 * W) {
+      hi[kblk_off(row, k, ld) >> 1] = 0u;
+      const size_t o = pair_off(row, k, ld);
+      *reinterpret_cast<uint16_t*>(p8 + o) = 0;
+      *reinterpret_cast<uint16_t*>(p8 + o + 16) = 0;
+    }
+  }
+  __device__ void pad_from(int k0, int sl, int W) {
+    for (int k = k0 + 8 * sl; k < ld; k += 8 * W) {
+      *reinterpret_cast<uint4*>(hi + (kblk_off(row, k, ld) >> 1)) = make_uint4(0u, 0u, 0u, 0u);
+      const size_t o = pair_off(row, k, ld);
+      *reinterpret_cast<uint2*>(p8 + o) = make_uint2(0u, 0u);
+      *reinterpret_cast<uint2*>(p8 + o + 16) = make_uint2(0u, 0u);
+    }
   }
 };
 
@@ -523,6 +588,22 @@ __global__ void init_lp_kernel(const InitProb* probs, const ChunkArgs* chp) {
   }
 }
 
+// fp16f8: Lh as init_lp_kernel<f16_t>; the pair plane holds e4m3(1 * 2^8)
+// at K = 0 and zeros elsewhere.
+__global__ void init_f16f8_kernel(const InitProb* probs, const ChunkArgs* chp) {
+  const ChunkArgs ch = *chp;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const InitProb a = probs[blockIdx.y];
+  if (i < ch.rows * a.ld) {
+    const int r = i / a.ld, k = i - r * a.ld;
+    ((f16_t*)a.L)[kblk_off((size_t)r, k, a.ld)] = (f16_t)(k == 0 ? 1.f : 0.f);
+    unsigned char* p8 = (unsigned char*)a.Ll + pair_off((size_t)r, k, a.ld);
+    p8[0] = k == 0 ? kE4M3_256 : 0;
+    p8[16] = 0;
+    if (k == 0) a.logp[a.logp_in_call ? ch.c0 + r : r] = 0.0;
+  }
+}
+
 __global__ void zero_int_kernel(int* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
@@ -541,6 +622,8 @@ hipError_t launch_init(int form, const InitProb* probs, int nprob, const ChunkAr
     const dim3 grid((unsigned)((n + 255) / 256), nprob);
     if (form == kBf16x3)
       hipLaunchKernelGGL(init_lp_kernel<bf16_t>, grid, dim3(256), 0, s, probs, ch);
+    else if (form == kFp16F8)
+      hipLaunchKernelGGL(init_f16f8_kernel, grid, dim3(256), 0, s, probs, ch);
     else
       hipLaunchKernelGGL(init_lp_kernel<f16_t>, grid, dim3(256), 0, s, probs, ch);
   }
@@ -574,6 +657,8 @@ hipError_t launch_measure(int form, const MeasureProb* probs, int nprob, const C
     launch_measure_t<kOutBf16x2>(displaced, grid_rows, nprob, probs, ch, seed, nflag, s);
   else if (form == kFp16x3)
     launch_measure_t<kOutF16x2>(displaced, grid_rows, nprob, probs, ch, seed, nflag, s);
+  else if (form == kFp16F8)
+    launch_measure_t<kOutF16F8>(displaced, grid_rows, nprob, probs, ch, seed, nflag, s);
   else
     launch_measure_t<kOutF16>(displaced, grid_rows, nprob, probs, ch, seed, nflag, s);
   return hipGetLastError();

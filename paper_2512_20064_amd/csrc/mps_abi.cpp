@@ -102,7 +102,7 @@ constexpr double kTuneMargin = 0.02;  // a candidate must beat the defaults by t
 
 int check_options(const mps_options* o) {
   if (o->precision != MPS_FP32 && o->precision != MPS_BF16X3 && o->precision != MPS_FP16 &&
-      o->precision != MPS_FP16X3)
+      o->precision != MPS_FP16X3 && o->precision != MPS_FP16F8)
     return fail(MPS_EINVAL, "unknown precision %d", o->precision);
   if (o->n_chunk < 0) return fail(MPS_EINVAL, "n_chunk < 0");
   if (o->max_device_bytes < 0) return fail(MPS_EINVAL, "max_device_bytes < 0");
@@ -116,10 +116,16 @@ int check_options(const mps_options* o) {
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 int lp_form(int precision) {
-  return precision == MPS_BF16X3 ? mps::kBf16x3 : precision == MPS_FP16X3 ? mps::kFp16x3 : mps::kFp16;
+  return precision == MPS_BF16X3   ? mps::kBf16x3
+         : precision == MPS_FP16X3 ? mps::kFp16x3
+         : precision == MPS_FP16F8 ? mps::kFp16F8
+                                   : mps::kFp16;
 }
-// hi + lo operand pairs (three products)
-bool is_split(int precision) { return precision == MPS_BF16X3 || precision == MPS_FP16X3; }
+// hi + lo operand pairs (a second plane per operand: the low parts, or for
+// MPS_FP16F8 the FP8 pair plane of the same size)
+bool is_split(int precision) {
+  return precision == MPS_BF16X3 || precision == MPS_FP16X3 || precision == MPS_FP16F8;
+}
 
 // Largest buffers a chain needs, per sample row (and the packed tensor).
 struct Shape {
@@ -128,12 +134,14 @@ struct Shape {
   int64_t qtmax = 1;   // max partial weights per sample
   int64_t kpmax = 64;  // max padded K of the 16-bit left vectors
   int64_t bmax = 1;    // max packed site-tensor elements
+  int64_t csmax = 1;   // max d_k * (padded chi_{k+1}): column scales (MPS_FP16F8)
 };
 
 struct ChainBufs {
   size_t L = 0, Lh = 0, Ll = 0, logp = 0;  // left-vector state (of chunk 0)
   size_t state = 0;                        // bytes from one chunk's state to the next
   size_t Bh = 0, Bl = 0, W = 0, qpart = 0;
+  size_t colscale = 0;
 };
 
 // Per-chain scratch for `rows` samples at byte offset `off`: `nstate` copies of
@@ -161,6 +169,7 @@ size_t chain_layout(int64_t rows, const Shape& sh, int precision, int64_t nstate
   if (precision != MPS_FP32) {
     b.Bh = take((size_t)sh.bmax * 2);
     if (is_split(precision)) b.Bl = take((size_t)sh.bmax * 2);
+    if (precision == MPS_FP16F8) b.colscale = take((size_t)sh.csmax * sizeof(float));
   }
   b.W = take((size_t)rows * sh.wmax * sizeof(float2));
   b.qpart = take((size_t)rows * sh.qtmax * sizeof(float));
@@ -202,6 +211,7 @@ int validate_chain(const Chain& c, int precision, Shape& sh, int idx) {
       const int CP = mps::lp_pad_cols(c.chi[k + 1]);
       sh.qtmax = std::max<int64_t>(sh.qtmax, (int64_t)c.d[k] * (CP / mps::kLpBNC));
       sh.bmax = std::max<int64_t>(sh.bmax, (int64_t)c.d[k] * CP * 2 * mps::lp_pad_k(c.chi[k]));
+      sh.csmax = std::max<int64_t>(sh.csmax, (int64_t)c.d[k] * CP);
     } else {
       sh.qtmax = std::max<int64_t>(sh.qtmax, (int64_t)c.d[k] * mps::col_tiles(c.chi[k + 1]));
     }
@@ -225,8 +235,9 @@ struct Step {
   int nprob = 0;
   int tn_total = 0;   // contraction column tiles over all problems of the step
   int blk_total = 0;  // packing blocks over all problems of the step
+  int cm_total = 0;   // column-scale blocks (MPS_FP16F8)
   int meas_rpw = 64;  // samples per wave in the measurement (set by the largest chi_r)
-  size_t contract = 0, tn_start = 0, pack = 0, blk_start = 0, measure = 0;  // offsets in the table blob
+  size_t contract = 0, tn_start = 0, pack = 0, blk_start = 0, measure = 0, cm_start = 0;  // offsets in the table blob
   double flops_per_row = 0, meas_bytes_per_row = 0;
 };
 
@@ -474,8 +485,8 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
     size_t t = 0;
     for (const Chain& c : chains)
       t += (size_t)c.M * (sizeof(mps::ContractProb) + sizeof(mps::ContractLpProb) + sizeof(mps::PackProb) +
-                          sizeof(mps::MeasureProb) + 2 * sizeof(int));
-    t += (size_t)B * sizeof(mps::InitProb) + (size_t)Mmax * 7 * 256 + 4096;
+                          sizeof(mps::MeasureProb) + 3 * sizeof(int));
+    t += (size_t)B * sizeof(mps::InitProb) + (size_t)Mmax * 8 * 256 + 4096;
     return t * (size_t)nstate + (size_t)nstate * sizeof(mps::ChunkArgs) + 512 + small_bytes;
   };
   auto scratch_for = [&](int64_t rows, std::vector<ChainBufs>* bufs) -> size_t {
@@ -574,7 +585,7 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
       std::vector<mps::ContractLpProb> cl;
       std::vector<mps::PackProb> pk;
       std::vector<mps::MeasureProb> ms;
-      std::vector<int> tns(1, 0), blks(1, 0);
+      std::vector<int> tns(1, 0), blks(1, 0), cms(1, 0);
       Step& sp = steps[(size_t)s * Mmax + k];
       for (int b = 0; b < B; ++b) {
         const Chain& c = chains[b];
@@ -584,11 +595,13 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
         if (lowp) {
           const int CP = mps::lp_pad_cols(chr), Kp = mps::lp_pad_k(K);
           T = CP / mps::kLpBNC;
-          mps::PackProb pp{site_A(b, k), at(bufs[b].Bh), split ? at(bufs[b].Bl) : nullptr, K, dk, chr, CP, Kp};
+          float* cs = o.precision == MPS_FP16F8 ? (float*)at(bufs[b].colscale) : nullptr;
+          mps::PackProb pp{site_A(b, k), at(bufs[b].Bh), split ? at(bufs[b].Bl) : nullptr, K, dk, chr, CP, Kp, cs};
           pk.push_back(pp);
           blks.push_back(blks.back() + (CP / 64) * (Kp / 64) * dk);
+          cms.push_back(cms.back() + (CP / 64) * dk);
           mps::ContractLpProb cp{sat(b, bufs[b].Lh), split ? sat(b, bufs[b].Ll) : nullptr, pp.Bh, pp.Bl,
-                                 (float2*)at(bufs[b].W), (float*)at(bufs[b].qpart), Kp, dk, chr, CP};
+                                 (float2*)at(bufs[b].W), (float*)at(bufs[b].qpart), Kp, dk, chr, CP, cs};
           cl.push_back(cp);
         } else {
           T = mps::col_tiles(chr);
@@ -629,10 +642,12 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
       sp.nprob = (int)ms.size();
       sp.tn_total = tns.back();
       sp.blk_total = blks.back();
+      sp.cm_total = cms.back();
       sp.contract = lowp ? tab.put(cl) : tab.put(cf);
       sp.tn_start = tab.put(tns);
       sp.pack = tab.put(pk);
       sp.blk_start = tab.put(blks);
+      sp.cm_start = tab.put(cms);
       sp.measure = tab.put(ms);
     }
   }
@@ -732,6 +747,10 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
     if (!lowp) return MPS_OK;
     const Step& sp = steps[k];
     MPS_TRY(mark(k, 0, stream));
+    if (form == mps::kFp16F8)
+      MPS_HIP(mps::launch_colscale((const mps::PackProb*)tp(sp.pack), (const int*)tp(sp.cm_start), sp.nprob,
+                                   sp.cm_total, stream),
+              "column-scale launch");
     MPS_HIP(mps::launch_pack_lp(site_form(k), (const mps::PackProb*)tp(sp.pack), (const int*)tp(sp.blk_start), sp.nprob,
                                 sp.blk_total, stream),
             "pack launch");

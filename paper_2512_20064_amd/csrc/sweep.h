@@ -47,7 +47,30 @@ __host__ __device__ inline size_t kblk_off(size_t r, int k, int Kp) {
 // the product with them is skipped, and the result is bit-identical to
 // kFp16x3 on the same tensor.  Packing and contraction only; the left
 // vectors are those of kFp16x3.
-enum LpForm { kBf16x3 = 1, kFp16 = 2, kFp16x3 = 3, kFp16x2 = 4 };
+//
+// kFp16F8: W = Lh*Bh (fp16 operands) plus the two correction products
+// Lh*Bl + Ll*Bh on the block-scaled FP8 MFMA (OCP E4M3 operands).  The site
+// tensor's complex column c is first divided by a power of two s_c (its
+// largest |re|, |im| then at most 448), Bs = B / s_c, Bh = fp16(Bs),
+// Bl = Bs - Bh; the left vector l (|l_i| <= 1 after renormalisation) splits
+// into Lh = fp16(l), Ll = l - Lh.  The FP8 operands carry fixed powers of
+// two, L8h = e4m3(Lh * 2^8), L8l = e4m3(Ll * 2^19), B8h = e4m3(Bh),
+// B8l = e4m3(Bl * 2^11), so that both corrections share the factor 2^-19
+// (the MFMA's uniform E8M0 scale), and W[:, c] = s_c * acc.  The FP8 parts
+// are stored as "pair planes": per row and 16-K slice, 16 bytes of the high
+// part then 16 bytes of the low part (the left vector: [L8h | L8l], the site
+// tensor: [B8l | B8h], so that byte p of a row meets byte p of a column in
+// one MFMA: L8h*B8l and L8l*B8h).  A pair plane has the byte size and
+// K-blocking of a 16-bit plane.
+enum LpForm { kBf16x3 = 1, kFp16 = 2, kFp16x3 = 3, kFp16x2 = 4, kFp16F8 = 5 };
+
+// Byte offset of K value k of row r in a pair plane (high part; the low part
+// is 16 bytes further): the 16-bit K-blocking with one byte per K value.
+__host__ __device__ inline size_t pair_off(size_t r, int k, int Kp) {
+  return ((r >> 8) * (size_t)(Kp >> 4) + (size_t)(k >> 4)) * 8192 + (r & 255) * 32 + (k & 15);
+}
+// E4M3 code of 256 = 2^8 (the first left vector, l = [1], times 2^8).
+constexpr unsigned char kE4M3_256 = 0x78;
 
 // Lanes of a wave that measure one sample: enough to gather the chosen branch
 // (chi_r complex) in pieces of 4, a power of two up to the whole wave.  A
@@ -80,8 +103,9 @@ struct ContractProb {
 struct PackProb {
   const float2* A;   // [K][d][chi_r] complex site tensor
   void* Bh;          // [d*CP*2][Kp] 16-bit real embedding, K contiguous
-  void* Bl;          // low parts (bf16x3 only)
+  void* Bl;          // low parts (split forms; kFp16F8: the FP8 pair plane)
   int K, d, chi_r, CP, Kp;
+  float* colscale;   // kFp16F8: [d*CP] power-of-two scale s_c per complex column
 };
 
 struct ContractLpProb {
@@ -92,6 +116,7 @@ struct ContractLpProb {
   float2* W;         // [rows][d*chi_r] complex FP32
   float* qpart;      // [rows][d*T], T = CP / kLpBNC
   int Kp, d, chi_r, CP;
+  const float* colscale;  // kFp16F8: [d*CP] column scales s_c
 };
 
 struct MeasureProb {
@@ -166,6 +191,10 @@ hipError_t launch_contract_f32(const ContractProb* probs, const int* tn_start, i
                                const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s);
 hipError_t launch_pack_lp(int form, const PackProb* probs, const int* blk_start, int nprob, int blk_total,
                           hipStream_t s);
+// kFp16F8: column scales of the problems' site tensors (before launch_pack_lp);
+// one workgroup per 64 complex columns of a branch, cm_start[p] = first
+// workgroup of problem p (nprob + 1 entries).
+hipError_t launch_colscale(const PackProb* probs, const int* cm_start, int nprob, int cm_total, hipStream_t s);
 hipError_t launch_contract_lp(int form, const ContractLpProb* probs, const int* tn_start, int nprob, int tn_total,
                               const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s);
 // displaced: the problems carry per-sample displacements (MeasureProb::mu);

@@ -47,7 +47,7 @@ def _assert_prefix_dependent(ref, seed, outcomes, rows, sites, n_index=None):
     return spreads
 
 
-@pytest.mark.parametrize("form", ["fp16x3", "bf16x3"])
+@pytest.mark.parametrize("form", ["fp16x3", "bf16x3", "fp16f8"])
 def test_chi10000_streamed_window_prefix_parity(form):
     """fp16x3 runs two MFMA products per complex product on these fp16-exact
     sites (the streamed workload's default); bf16x3 runs three."""

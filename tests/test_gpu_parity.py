@@ -31,12 +31,12 @@ def mpsmod():
 # small-bond kernel (FP32 in every form); "fp32-steps" and the 16-bit forms
 # here force the per-site launches, so that the 16-bit kernels are the ones
 # tested on small chains too.
-FORMS = ["fp32", "fp32-steps", "bf16x3", "fp16", "fp16x3"]
+FORMS = ["fp32", "fp32-steps", "bf16x3", "fp16", "fp16x3", "fp16f8"]
 # Forms held to the stated probability bars (FP32 1e-5, low precision 1e-3).
 # The single-product fp16 form does not meet 1e-3 beyond a few sites; its
 # error is measured against a looser derived bound in test_fp16_error_report.
-PARITY_FORMS = ["fp32", "fp32-steps", "bf16x3", "fp16x3"]
-EPS = {"fp32": 1e-5, "fp32-steps": 1e-5, "bf16x3": 1e-3, "fp16": 1e-3, "fp16x3": 1e-3}
+PARITY_FORMS = ["fp32", "fp32-steps", "bf16x3", "fp16x3", "fp16f8"]
+EPS = {"fp32": 1e-5, "fp32-steps": 1e-5, "bf16x3": 1e-3, "fp16": 1e-3, "fp16x3": 1e-3, "fp16f8": 1e-3}
 
 
 def _sampler(mpsmod, form, **kw):

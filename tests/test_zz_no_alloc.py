@@ -52,6 +52,7 @@ CASES = [
     ("fp32", 0, (5, 24, 4, 32, 4096), (6, 10, 2, 16, 333)),      # persistent small-bond kernel
     ("bf16x3", 1, (7, 20, 4, 64, 3000), (8, 12, 4, 40, 900)),
     ("fp16x3", 1, (9, 16, 3, 96, 2048), (10, 9, 2, 64, 257)),
+    ("fp16f8", 1, (13, 14, 4, 128, 2048), (14, 9, 3, 64, 300)),
 ]
 
 
