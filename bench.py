@@ -515,7 +515,8 @@ def run_batch_bench(args):
 
 
 WORKLOAD_DEFAULTS = {
-    "resident": {"sites": 1024, "chi": 1024, "pool": 16, "chunk": 65536, "precision": "bf16x3", "beside": "fp32"},
+    "resident": {"sites": 1024, "chi": 1024, "pool": 16, "chunk": 65536, "precision": "fp16f8",
+                 "beside": "bf16x3,fp32"},
     "small": {"sites": 32, "chi": 32, "pool": 1, "chunk": 4096, "precision": "fp32", "beside": ""},
     "uneven": {"sites": 2048, "chi": 4096, "pool": 2, "chunk": 8192, "precision": "bf16x3", "beside": ""},
     "stream": {"sites": 64, "chi": 10000, "pool": 4, "chunk": 65536, "samples": 1 << 17, "precision": "fp16x3",

@@ -355,22 +355,27 @@ __device__ inline unsigned e4m3x4(float a, float b, float c, float d) {
   return (unsigned)w;
 }
 
-// Column scales: one workgroup per 64 complex columns of one branch; 4 row
-// phases of 64 threads, maximum of |re| and |im| over the column.
-__global__ __launch_bounds__(256) void colscale_kernel(const PackProb* probs, const int* cm_start, int nprob) {
+// Column maxima: one workgroup per (row block, branch, 64 complex columns);
+// 4 row phases of 64 threads, maximum of |re| and |im| over the block's rows.
+__global__ __launch_bounds__(256) void colmax_kernel(const PackProb* probs, const int* cm_start, int nprob) {
   __shared__ float part[4][64];
   const int p = find_problem(cm_start, nprob, blockIdx.x);
   const PackProb a = probs[p];
-  const int wb = blockIdx.x - cm_start[p];
   const int ncb = a.CP / 64;
-  const int br = wb / ncb;
-  const int c = (wb - br * ncb) * 64 + (threadIdx.x & 63);
+  const int wb = blockIdx.x - cm_start[p];
+  const int rb = wb / (a.d * ncb);
+  const int rest = wb - rb * (a.d * ncb);
+  const int br = rest / ncb;
+  const int c = (rest - br * ncb) * 64 + (threadIdx.x & 63);
   const int ph = threadIdx.x >> 6;
+  const int RB = colmax_blocks(a.K);
+  const int rpb = (a.K + RB - 1) / RB;
+  const int l1 = min(a.K, (rb + 1) * rpb);
   float m = 0.f;
   if (c < a.chi_r) {
     const size_t pitch = (size_t)a.d * a.chi_r;
     const float2* col = a.A + (size_t)br * a.chi_r + c;
-    for (int l = ph; l < a.K; l += 4) {
+    for (int l = rb * rpb + ph; l < l1; l += 4) {
       const float2 z = col[(size_t)l * pitch];
       m = fmaxf(m, fmaxf(fabsf(z.x), fabsf(z.y)));
     }
@@ -380,7 +385,7 @@ __global__ __launch_bounds__(256) void colscale_kernel(const PackProb* probs, co
   if (threadIdx.x < 64) {
     const float mm = fmaxf(fmaxf(part[0][threadIdx.x], part[1][threadIdx.x]),
                            fmaxf(part[2][threadIdx.x], part[3][threadIdx.x]));
-    a.colscale[(size_t)br * a.CP + c] = pow2_scale(mm);
+    a.colpart[(size_t)rb * a.d * a.CP + (size_t)br * a.CP + c] = mm;
   }
 }
 
@@ -407,6 +412,24 @@ __global__ __launch_bounds__(256) void pack_f16f8_kernel(const PackProb* probs, 
     tile[l][c] = (gl < a.K && gc < a.chi_r) ? a.A[(size_t)gl * pitch + (size_t)br * a.chi_r + gc]
                                             : make_float2(0.f, 0.f);
   }
+  // column scales of the tile's 64 columns from the row-block maxima; the
+  // workgroups of the first K block also store them for the contraction
+  __shared__ float inv_sh[PK_C];
+  {
+    __shared__ float mpart[4][PK_C];
+    const int RB = colmax_blocks(a.K);
+    const int c = tid & (PK_C - 1), ph = tid >> 6;
+    const float* cp = a.colpart + (size_t)br * a.CP + c0 + c;
+    float m = 0.f;
+    for (int rb = ph; rb < RB; rb += 4) m = fmaxf(m, cp[(size_t)rb * a.d * a.CP]);
+    mpart[ph][c] = m;
+    __syncthreads();
+    if (tid < PK_C) {
+      const float s = pow2_scale(fmaxf(fmaxf(mpart[0][tid], mpart[1][tid]), fmaxf(mpart[2][tid], mpart[3][tid])));
+      inv_sh[tid] = 1.f / s;  // exact: a power of two
+      if (l0 == 0) a.colscale[(size_t)br * a.CP + c0 + tid] = s;
+    }
+  }
   __syncthreads();
   f16_t* Bh = (f16_t*)a.Bh;
   unsigned char* B8 = (unsigned char*)a.Bl;
@@ -415,7 +438,7 @@ __global__ __launch_bounds__(256) void pack_f16f8_kernel(const PackProb* probs, 
     const int idx = it * 256 + tid;
     const int rowl = idx >> 3, ch = idx & 7;
     const int c = rowl >> 1, p = rowl & 1;
-    const float inv = 1.f / a.colscale[(size_t)br * a.CP + c0 + c];  // exact: a power of two
+    const float inv = inv_sh[c];
     float v[8];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -682,7 +705,7 @@ hipError_t launch_contract_t(const ContractLpProb* probs, const int* tn_start, i
 
 hipError_t launch_colscale(const PackProb* probs, const int* cm_start, int nprob, int cm_total, hipStream_t s) {
   if (nprob <= 0 || cm_total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(colscale_kernel, dim3(cm_total), dim3(256), 0, s, probs, cm_start, nprob);
+  hipLaunchKernelGGL(colmax_kernel, dim3(cm_total), dim3(256), 0, s, probs, cm_start, nprob);
   return hipGetLastError();
 }
 

@@ -141,7 +141,7 @@ struct ChainBufs {
   size_t L = 0, Lh = 0, Ll = 0, logp = 0;  // left-vector state (of chunk 0)
   size_t state = 0;                        // bytes from one chunk's state to the next
   size_t Bh = 0, Bl = 0, W = 0, qpart = 0;
-  size_t colscale = 0;
+  size_t colscale = 0, colpart = 0;
 };
 
 // Per-chain scratch for `rows` samples at byte offset `off`: `nstate` copies of
@@ -169,7 +169,10 @@ size_t chain_layout(int64_t rows, const Shape& sh, int precision, int64_t nstate
   if (precision != MPS_FP32) {
     b.Bh = take((size_t)sh.bmax * 2);
     if (is_split(precision)) b.Bl = take((size_t)sh.bmax * 2);
-    if (precision == MPS_FP16F8) b.colscale = take((size_t)sh.csmax * sizeof(float));
+    if (precision == MPS_FP16F8) {
+      b.colscale = take((size_t)sh.csmax * sizeof(float));
+      b.colpart = take((size_t)sh.csmax * 16 * sizeof(float));
+    }
   }
   b.W = take((size_t)rows * sh.wmax * sizeof(float2));
   b.qpart = take((size_t)rows * sh.qtmax * sizeof(float));
@@ -595,11 +598,13 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
         if (lowp) {
           const int CP = mps::lp_pad_cols(chr), Kp = mps::lp_pad_k(K);
           T = CP / mps::kLpBNC;
-          float* cs = o.precision == MPS_FP16F8 ? (float*)at(bufs[b].colscale) : nullptr;
-          mps::PackProb pp{site_A(b, k), at(bufs[b].Bh), split ? at(bufs[b].Bl) : nullptr, K, dk, chr, CP, Kp, cs};
+          const bool f8 = o.precision == MPS_FP16F8;
+          float* cs = f8 ? (float*)at(bufs[b].colscale) : nullptr;
+          mps::PackProb pp{site_A(b, k), at(bufs[b].Bh), split ? at(bufs[b].Bl) : nullptr, K, dk, chr, CP, Kp, cs,
+                           f8 ? (float*)at(bufs[b].colpart) : nullptr};
           pk.push_back(pp);
           blks.push_back(blks.back() + (CP / 64) * (Kp / 64) * dk);
-          cms.push_back(cms.back() + (CP / 64) * dk);
+          cms.push_back(cms.back() + mps::colmax_blocks(K) * (CP / 64) * dk);
           mps::ContractLpProb cp{sat(b, bufs[b].Lh), split ? sat(b, bufs[b].Ll) : nullptr, pp.Bh, pp.Bl,
                                  (float2*)at(bufs[b].W), (float*)at(bufs[b].qpart), Kp, dk, chr, CP, cs};
           cl.push_back(cp);

@@ -106,7 +106,10 @@ struct PackProb {
   void* Bl;          // low parts (split forms; kFp16F8: the FP8 pair plane)
   int K, d, chi_r, CP, Kp;
   float* colscale;   // kFp16F8: [d*CP] power-of-two scale s_c per complex column
+  float* colpart;    // kFp16F8: [colmax_blocks(K)][d*CP] column maxima of row blocks
 };
+// kFp16F8 column maxima: the K rows of a site tensor in at most 16 blocks.
+__host__ __device__ inline int colmax_blocks(int K) { return K < 64 * 16 ? (K + 63) / 64 : 16; }
 
 struct ContractLpProb {
   const void* Lh;    // [rows_alloc][Kp] 16-bit left vectors (interleaved re, im), K padded with 0
@@ -191,9 +194,10 @@ hipError_t launch_contract_f32(const ContractProb* probs, const int* tn_start, i
                                const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s);
 hipError_t launch_pack_lp(int form, const PackProb* probs, const int* blk_start, int nprob, int blk_total,
                           hipStream_t s);
-// kFp16F8: column scales of the problems' site tensors (before launch_pack_lp);
-// one workgroup per 64 complex columns of a branch, cm_start[p] = first
-// workgroup of problem p (nprob + 1 entries).
+// kFp16F8: column maxima of the problems' site tensors per row block (before
+// launch_pack_lp, which reduces them to the column scales); one workgroup per
+// (row block, branch, 64 complex columns), cm_start[p] = first workgroup of
+// problem p (nprob + 1 entries).
 hipError_t launch_colscale(const PackProb* probs, const int* cm_start, int nprob, int cm_total, hipStream_t s);
 hipError_t launch_contract_lp(int form, const ContractLpProb* probs, const int* tn_start, int nprob, int tn_total,
                               const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s);
