@@ -322,6 +322,51 @@ int mps_autotune(mps_handle h, const void* const* tensors, int32_t dtype,
                  const int32_t* chi, const int32_t* d, int32_t M, int64_t N,
                  uint64_t seed, mps_tune_report* rep);
 
+/* Contraction tile shapes.  Every precision form has two; both give the same
+ * bits (each output is accumulated over K in the same order, and the branch
+ * weights are summed from partials of 32 complex columns whatever the tile):
+ *   MPS_TILE_WIDE    FP32 128 samples x 64 complex columns; 16-bit and
+ *                    MPS_FP16F8 256 x 128 (the default);
+ *   MPS_TILE_NARROW  FP32 64 x 64; 16-bit and MPS_FP16F8 256 x 64 (half the
+ *                    column padding for thin bonds, twice the workgroups).  */
+#define MPS_TILE_WIDE 0
+#define MPS_TILE_NARROW 1
+
+/* The tile of one site shape (chi_l, d, chi_r) at `rows` samples per
+ * contraction launch (the chunk), with the timings it was chosen from. */
+typedef struct {
+  int32_t chi_l, d, chi_r;
+  int32_t tile;               /* MPS_TILE_WIDE or MPS_TILE_NARROW             */
+  int64_t rows;               /* samples per launch the choice applies to     */
+  double ms_wide, ms_narrow;  /* timed contraction launch (0: not timed)      */
+} mps_tile_choice;
+
+/*
+ * Tile autotuner (Section 3.4.2: site-varying bond dimensions, so each site
+ * shape gets its own choice).  For every distinct site shape of the chains
+ * that take per-site launches (chains handled by the persistent small-bond
+ * kernel are skipped), in the handle's precision form: the site tensor is
+ * packed with each tile's padding and one contraction launch of `rows`
+ * samples is timed per tile (one warm-up, three timed; operand noise of the
+ * sweep's magnitudes in the left vectors).  The narrow tile is chosen when it
+ * is at least 2 % faster.  The choices are stored in the handle, keyed by
+ * (chi_l, d, chi_r, rows), and used by later mps_sample / mps_sample_batch /
+ * mps_sample_noalloc calls whose chunk is `rows` (other shapes and chunks
+ * take the wide tile).  Results are bit-identical whatever the choice.
+ * chains: B chains as in mps_sample_batch (device-resident complex64 sites;
+ * outcomes and logp are not used).  out: up to cap choices (may be NULL if
+ * cap = 0); *n_out (may be NULL) receives the number of distinct shapes.
+ * Allocates timing scratch for the call and frees it.  Returns MPS_OK or an
+ * error as mps_sample.
+ */
+int mps_autotune_tiles(mps_handle h, int32_t B, const mps_chain* chains, int64_t rows, uint64_t seed,
+                       mps_tile_choice* out, int32_t cap, int32_t* n_out);
+
+/* Install tile choices (e.g. read back from a cache of an earlier
+ * mps_autotune_tiles); n = 0 clears the handle's choices.  Checked on the
+ * host only. */
+int mps_set_tiles(mps_handle h, const mps_tile_choice* choices, int32_t n);
+
 /* Counters of the last mps_sample / mps_sample_batch call on this handle. */
 int mps_get_stats(mps_handle h, mps_stats* st);
 

@@ -30,28 +30,34 @@ namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int BM = kBM;
 constexpr int BNC = kBNC;
 constexpr int BK = kBK;
-constexpr int NTHR = 256;
-// L stage: two planes (re, im), each [BK][LP] floats, transposed so that the
-// 32 lanes feeding one MFMA read 32 consecutive floats.  The +4 pitch and the
-// +32 offset of the im plane keep the transposed stores and the reads free
-// of bank aliasing.
-constexpr int LP = BM + 4;
-constexpr int LIM = BK * LP + 32;
-constexpr int LFL = LIM + BK * LP;
-// A stage: [BK][2*BNC] floats, rows of the site tensor as stored.
-constexpr int AP = 2 * BNC;
-constexpr int AFL = BK * AP;
-constexpr int STAGE = LFL + AFL;
-constexpr int LLOADS = BM * BK / NTHR;
-constexpr int ALOADS = BK * BNC / NTHR;
-static_assert(BM * BK % NTHR == 0 && BK * BNC % NTHR == 0, "tile loads must divide evenly");
-static_assert(BM == 128 && BNC == 64, "wave layout below assumes a 128 x 64 (complex) tile");
+static_assert(BNC == 64, "wave layout below assumes 64 complex columns per tile");
 
-// Four waves in a 2 x 2 grid; each owns 64 rows x 32 complex columns, i.e.
-// 2 x 2 output blocks of 32 rows x 16 complex (32 real) columns.
+// Tile of BM rows (128: the wide variant, 4 waves; 64: the narrow one, 2
+// waves) by 64 complex columns.
+//   L stage: two planes (re, im), each [BK][LP] floats, transposed so that
+//   the 32 lanes feeding one MFMA read 32 consecutive floats.  The +4 pitch
+//   and the +32 offset of the im plane keep the transposed stores and the
+//   reads free of bank aliasing.
+//   A stage: [BK][2*BNC] floats, rows of the site tensor as stored.
+template <int BM>
+struct F32Tile {
+  static constexpr int NTHR = 2 * BM;
+  static constexpr int LP = BM + 4;
+  static constexpr int LIM = BK * LP + 32;
+  static constexpr int LFL = LIM + BK * LP;
+  static constexpr int AP = 2 * BNC;
+  static constexpr int AFL = BK * AP;
+  static constexpr int STAGE = LFL + AFL;
+  static constexpr int LLOADS = BM * BK / NTHR;
+  static constexpr int ALOADS = BK * BNC / NTHR;
+  static_assert(BM * BK % NTHR == 0 && BK * BNC % NTHR == 0, "tile loads must divide evenly");
+};
+
+// Waves in a (BM/64) x 2 grid; each owns 64 rows x 32 complex columns, i.e.
+// 2 x 2 output blocks of 32 rows x 16 complex (32 real) columns, so both
+// variants run the same per-wave code and give the same bits.
 //
 // Accumulation is two-level: each K tile (BK complex = 2*BK real terms) is
 // summed into fresh MFMA accumulators, which are then added to running FP32
@@ -59,9 +65,14 @@ static_assert(BM == 128 && BNC == 64, "wave layout below assumes a 128 x 64 (com
 // of order u*sqrt(K) per output; blocking it into K/BK partial sums cuts that
 // by about sqrt(BK), which matters because the rounding error of the left
 // vector is carried from site to site.
-__global__ __launch_bounds__(NTHR, 2) void contract_f32_kernel(const ContractProb* probs, const int* tn_start,
-                                                              int nprob, int tn_total, int tiles_m, int per_xcd,
-                                                              int group_m, const ChunkArgs* chp) {
+template <int BM>
+__global__ __launch_bounds__(F32Tile<BM>::NTHR, 2) void contract_f32_kernel(const ContractProb* probs,
+                                                                          const int* tn_start, int nprob,
+                                                                          int tn_total, int tiles_m, int per_xcd,
+                                                                          int group_m, const ChunkArgs* chp) {
+  typedef F32Tile<BM> Tl;
+  constexpr int NTHR = Tl::NTHR, LP = Tl::LP, LIM = Tl::LIM, LFL = Tl::LFL, AP = Tl::AP, STAGE = Tl::STAGE;
+  constexpr int LLOADS = Tl::LLOADS, ALOADS = Tl::ALOADS;
   __shared__ float lds[2 * STAGE];
   const int rows = chp->rows;
 
@@ -203,10 +214,11 @@ __global__ __launch_bounds__(NTHR, 2) void contract_f32_kernel(const ContractPro
     }
   }
 
-  // Epilogue 2: partial weight of this (row, branch, column tile).  Columns
-  // past chi_r were zero-filled, so they add nothing.  Reduction order is
-  // fixed (lanes by xor butterfly, then the two column halves of the tile),
-  // so the result does not depend on scheduling.
+  // Epilogue 2: partial weights per 32 complex columns (one per wave column
+  // of the tile).  Columns past chi_r were zero-filled, so they add nothing.
+  // Reduction order is fixed (the two blocks of a lane, then the lanes by xor
+  // butterfly), so the result depends neither on scheduling nor on the
+  // variant.
   float* red = lds;  // the stages are free: the K loop ended on a barrier
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb) {
@@ -217,27 +229,41 @@ __global__ __launch_bounds__(NTHR, 2) void contract_f32_kernel(const ContractPro
       for (int cb = 0; cb < 2; ++cb) s += tot[rb][cb][v] * tot[rb][cb][v];
 #pragma unroll
       for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off, 32);
-      if (j == 0) red[(wave & 1) * BM + wr + rb * 32 + (v >> 2) * 8 + half * 4 + (v & 3)] = s;
+      if (j == 0) red[(wr + rb * 32 + (v >> 2) * 8 + half * 4 + (v & 3)) * 2 + (wave & 1)] = s;
     }
   }
   __syncthreads();
   if (tid < BM) {
     const int gr = m0 + tid;
-    if (gr < rows) a.qpart[(size_t)gr * (a.d * T) + branch * T + ct] = red[tid] + red[BM + tid];
+    const int TP = fp32_parts(a.chi_r);
+    if (gr < rows) {
+      float* dst = a.qpart + (size_t)gr * (a.d * TP) + branch * TP + 2 * ct;
+      dst[0] = red[2 * tid];
+      dst[1] = red[2 * tid + 1];
+    }
   }
 }
 
 }  // namespace
 
-hipError_t launch_contract_f32(const ContractProb* probs, const int* tn_start, int nprob, int tn_total,
-                               const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s) {
+namespace {
+template <int BM>
+hipError_t launch_f32_t(const ContractProb* probs, const int* tn_start, int nprob, int tn_total, const ChunkArgs* ch,
+                        int grid_rows, int group_m, hipStream_t s) {
   const int tiles_m = (grid_rows + BM - 1) / BM;
   const long long ntiles = (long long)tiles_m * tn_total;
   if (ntiles <= 0 || nprob <= 0) return hipSuccess;
   const int per_xcd = (int)((ntiles + 7) / 8);
-  hipLaunchKernelGGL(contract_f32_kernel, dim3(per_xcd * 8), dim3(NTHR), 0, s, probs, tn_start, nprob, tn_total,
-                     tiles_m, per_xcd, group_m, ch);
+  hipLaunchKernelGGL(contract_f32_kernel<BM>, dim3(per_xcd * 8), dim3(F32Tile<BM>::NTHR), 0, s, probs, tn_start,
+                     nprob, tn_total, tiles_m, per_xcd, group_m, ch);
   return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_contract_f32(int tile, const ContractProb* probs, const int* tn_start, int nprob, int tn_total,
+                               const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s) {
+  if (tile == kTileNarrow) return launch_f32_t<64>(probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s);
+  return launch_f32_t<128>(probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s);
 }
 
 }  // namespace mps

@@ -119,14 +119,20 @@ __global__ __launch_bounds__(256) void pack_kernel(const PackProb* probs, const 
 // ------------------------------------------------------------ contract ----
 
 constexpr int BM = kLpBM;            // rows (samples) per workgroup
-constexpr int BN = 2 * kLpBNC;       // real columns per workgroup
 constexpr int BK = kLpBK;            // real K per pipeline stage
-constexpr int NTHR = 512;            // 8 waves: 4 (rows) x 2 (columns)
-constexpr int NST = 5;               // pipeline stages in LDS (5 x 32 KiB = the whole 160 KiB for bf16x3)
-constexpr int AHEAD = NST - 1;       // stages issued before the first one is read
-static_assert(AHEAD <= 4, "the shortest K (64 real values) has 4 stages");
-constexpr int ARR = BM * BK * 2;     // bytes of one operand tile in a stage (8 KiB)
-static_assert(BM == 256 && BN == 256 && BK == 16, "layout below assumes 256 x 256 x 16");
+constexpr int ARR = BM * BK * 2;     // bytes of one left-vector tile in a stage (8 KiB)
+static_assert(BM == 256 && BK == 16, "layout below assumes 256-row tiles and 16-K stages");
+
+// Tile variants (sweep.h): NWC wave columns of 64 rows x 128 real columns
+// each, over 4 wave rows.  Wide: NWC = 2, a 256 x 256 real tile of 8 waves;
+// narrow: NWC = 1, 256 x 128 real, 4 waves.  Every wave runs the same code on
+// the same 64 x 128 block shape, so both variants give the same bits.
+template <int NWC>
+struct LpTile {
+  static constexpr int BN = 128 * NWC;            // real columns (packed rows) per workgroup
+  static constexpr int NTHR = 256 * NWC;          // 4 x NWC waves
+  static constexpr int BARR = BN * BK * 2;        // bytes of one site-tensor tile in a stage
+};
 
 // LDS rows are 32 bytes (16 K values = 2 chunks of 16 bytes).  The chunk is
 // XOR-swizzled by row bits 2 and 3 so that the 16-byte reads of 8 or 16
@@ -139,25 +145,86 @@ __device__ inline int lds_off(int row, int chunk) { return row * 32 + ((chunk ^ 
 // is not waited on.
 constexpr unsigned vmcnt_lgkm0_imm(unsigned n) { return (n & 0xF) | (0x7u << 4); }
 
+// Load instruction idx (0 .. groups-1) of a stage: one KiB = 32 rows of one
+// operand tile.  The NL left-vector tiles come first (8 row groups each),
+// then the NB site-tensor tiles (BN/32 row groups each).
+template <int NWC>
+__device__ inline void load_slot(int idx, int NL, int& q, int& rg, int& ldst) {
+  constexpr int GB = LpTile<NWC>::BN / 32;
+  if (idx < NL * 8) {
+    q = idx >> 3;
+    rg = idx & 7;
+    ldst = q * ARR + rg * 1024;
+  } else {
+    const int ib = idx - NL * 8;
+    q = NL + ib / GB;
+    rg = ib % GB;
+    ldst = NL * ARR + (q - NL) * LpTile<NWC>::BARR + rg * 1024;
+  }
+}
+
+// Partial branch weights of the tile (fixed granularity: 32 complex columns
+// = cb blocks {0,1} and {2,3} of a wave), summed per lane over the two
+// blocks, across the 32 lanes of a half by an xor butterfly, staged in LDS
+// and stored as one run of partials per row.  The order of every addition is
+// the same in every variant.
+template <int NWC>
+__device__ inline void store_partials(const floatx16 (&acc)[2][4], float* red, int wave, int wr, int half, int j,
+                                      int tid, int m0, int rows, float* qpart, size_t qrow, int q0) {
+  constexpr int NG = 2 * NWC;  // 32-column groups per tile
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        float s = acc[rb][2 * g][v] * acc[rb][2 * g][v];
+        s += acc[rb][2 * g + 1][v] * acc[rb][2 * g + 1][v];
+#pragma unroll
+        for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off, 32);
+        const int r = wr + rb * 32 + (v >> 2) * 8 + half * 4 + (v & 3);
+        if (j == 0) red[r * NG + (NWC == 2 ? (wave & 1) * 2 : 0) + g] = s;
+      }
+    }
+  }
+  __syncthreads();
+  if (tid < BM) {
+    const int gr = m0 + tid;
+    if (gr < rows) {
+      float* dst = qpart + (size_t)gr * qrow + q0;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) dst[g] = red[tid * NG + g];
+    }
+  }
+}
+
 // Pipeline: stage kt lives in LDS buffer kt % NST.  Operand tiles go straight
 // from memory into LDS (global_load_lds_dwordx4: no staging registers and no
-// LDS store phase), four stages ahead of the stage being read from LDS,
+// LDS store phase), NST-1 stages ahead of the stage being read from LDS,
 // which is itself one stage ahead of the MFMAs (see open_stage below).
-// One stage of MFMAs is ~1500 cycles per SIMD.
-template <typename T, int NPROD>
-__global__ __launch_bounds__(NTHR, 1) void contract_lp_kernel(const ContractLpProb* probs, const int* tn_start,
-                                                             int nprob, int tn_total, int tiles_m, int per_xcd,
-                                                             int group_m, const ChunkArgs* chp) {
+// One stage of MFMAs is ~1500 cycles per SIMD.  The wide variant has a
+// 5-stage ring (5 x 32 KiB = the whole 160 KiB for bf16x3, one workgroup
+// per CU); the narrow one a 3-stage ring (3 x 24 KiB), two workgroups per CU.
+template <typename T, int NPROD, int NWC>
+__global__ __launch_bounds__(LpTile<NWC>::NTHR, 1) void contract_lp_kernel(const ContractLpProb* probs,
+                                                                          const int* tn_start, int nprob,
+                                                                          int tn_total, int tiles_m, int per_xcd,
+                                                                          int group_m, const ChunkArgs* chp) {
   typedef typename Vec8<T>::type V8;
+  typedef LpTile<NWC> Tile;
   // Products per complex product: 3 = Lh*Bh + Lh*Bl + Ll*Bh (split form);
   // 2 = Lh*Bh + Ll*Bh (split left vectors, site tensor exact in T, so Bl = 0
   // and the omitted product adds exact zeros); 1 = Lh*Bh.
   constexpr int NL = NPROD >= 2 ? 2 : 1;    // left-vector tiles per stage: Ah, [Al]
   constexpr int NB = NPROD == 3 ? 2 : 1;    // site-tensor tiles per stage: Bh, [Bl]
-  constexpr int NARR = NL + NB;
-  constexpr int STAGE = NARR * ARR;
-  constexpr int IPW = NARR;                 // 1 KiB load instructions per wave per stage
-  constexpr int IB = NL;                    // index of the Bh tile in a stage
+  constexpr int NST = NWC == 2 ? 5 : 3;
+  constexpr int STAGE = NL * ARR + NB * Tile::BARR;
+  constexpr int GROUPS = NL * 8 + NB * (Tile::BN / 32);
+  constexpr int NWAVE = 4 * NWC;
+  static_assert(GROUPS % NWAVE == 0, "loads must divide evenly over the waves");
+  constexpr int IPW = GROUPS / NWAVE;        // 1 KiB load instructions per wave per stage
+  static_assert((NST - 2) * IPW <= 15, "vmcnt immediates below");
+  constexpr int BOFF = NL * ARR;             // offset of the Bh tile in a stage
   __shared__ __attribute__((aligned(16))) char lds[NST * STAGE];
 
   int tm, tng;
@@ -166,18 +233,20 @@ __global__ __launch_bounds__(NTHR, 1) void contract_lp_kernel(const ContractLpPr
   const int p = find_problem(tn_start, nprob, tng);
   const ContractLpProb a = probs[p];
   const int tn = tng - tn_start[p];
-  const int T_ = a.CP / kLpBNC;
-  const int branch = tn / T_;
-  const int ct = tn - branch * T_;
+  const int TC = a.CP / (Tile::BN / 2);     // column tiles per branch
+  const int branch = tn / TC;
+  const int ct = tn - branch * TC;
   const int m0 = tm * BM;
-  const int c0 = ct * kLpBNC;                               // first complex column within the branch
-  const size_t cblk = ((size_t)branch * a.CP + c0) * 2 / BM;  // 256-row block of the packed tensor
+  const int c0 = ct * (Tile::BN / 2);                        // first complex column within the branch
+  const size_t prow = ((size_t)branch * a.CP + c0) * 2;      // first packed row of the tile
+  const size_t cblk = prow >> 8;                             // its 256-row block
+  const int crow = (int)(prow & 255);                        // and row within the block (0 or 128)
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wr = (wave >> 1) * 64;
-  const int wc = (wave & 1) * 128;  // real columns
+  const int wr = (wave / NWC) * 64;
+  const int wc = (wave % NWC) * 128;  // real columns
   const int half = lane >> 5;
   const int j = lane & 31;
 
@@ -187,15 +256,15 @@ __global__ __launch_bounds__(NTHR, 1) void contract_lp_kernel(const ContractLpPr
   int ldst[IPW];
 #pragma unroll
   for (int i = 0; i < IPW; ++i) {
-    const int idx = wave * IPW + i;
-    const int q = idx >> 3, rg = idx & 7;
-    const bool is_b = q >= IB;
-    const int qq = is_b ? q - IB : q;  // 0 = hi, 1 = lo
+    int q, rg, dst;
+    load_slot<NWC>(wave * IPW + i, NL, q, rg, dst);
+    const bool is_b = q >= NL;
+    const int qq = is_b ? q - NL : q;  // 0 = hi, 1 = lo
     const T* base = is_b ? (const T*)(qq ? a.Bl : a.Bh) + cblk * kbs : (const T*)(qq ? a.Ll : a.Lh) + (size_t)tm * kbs;
-    const int row = rg * 32 + (lane >> 1);
+    const int row = rg * 32 + (lane >> 1) + (is_b ? crow : 0);
     const int lc = (lane & 1) ^ swz(row);
     src[i] = base + row * 16 + lc * 8;
-    ldst[i] = q * ARR + rg * 1024;
+    ldst[i] = dst;
   }
   auto issue = [&](int kt) {
     char* st = lds + (kt % NST) * STAGE;
@@ -230,8 +299,8 @@ __global__ __launch_bounds__(NTHR, 1) void contract_lp_kernel(const ContractLpPr
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) {
       const int row = wc + cb * 32 + j;
-      o.bh[cb] = *reinterpret_cast<const V8*>(st + IB * ARR + lds_off(row, half));
-      if (NB == 2) o.bl[cb] = *reinterpret_cast<const V8*>(st + (IB + 1) * ARR + lds_off(row, half));
+      o.bh[cb] = *reinterpret_cast<const V8*>(st + BOFF + lds_off(row, half));
+      if (NB == 2) o.bl[cb] = *reinterpret_cast<const V8*>(st + BOFF + Tile::BARR + lds_off(row, half));
     }
   };
   auto mma = [&](const Ops& o) {
@@ -247,9 +316,9 @@ __global__ __launch_bounds__(NTHR, 1) void contract_lp_kernel(const ContractLpPr
   // Make stage s readable by every wave: wait for this wave's own loads of
   // stage s (the `issued - 1 - s` stages issued after it may stay in flight)
   // and for this wave's LDS reads, then one barrier.  In the steady state
-  // `issued` = s + 4 on entry, so the load issued after the barrier (stage
-  // s + 4) goes into buffer (s + 4) % NST = (s - 1) % NST, the buffer of
-  // stage s - 1, whose LDS reads every wave issued in the previous step: the
+  // `issued` = s + NST - 1 on entry, so the load issued after the barrier
+  // (stage s + NST - 1) goes into buffer (s - 1) % NST, the buffer of stage
+  // s - 1, whose LDS reads every wave issued in the previous step: the
   // LDS-read wait before the barrier is what makes that overwrite safe.  It
   // costs nothing (those reads were issued a whole stage of MFMAs earlier).
   const int nkt = a.Kp / BK;  // a multiple of 4: Kp is a multiple of 64
@@ -265,7 +334,7 @@ __global__ __launch_bounds__(NTHR, 1) void contract_lp_kernel(const ContractLpPr
   };
 
 #pragma unroll
-  for (int i = 0; i < AHEAD; ++i) issue(issued++);
+  for (int i = 0; i < NST - 1; ++i) issue(issued++);
   Ops o0, o1;
   open_stage(0);
   lds_read(0, o0);
@@ -302,28 +371,11 @@ __global__ __launch_bounds__(NTHR, 1) void contract_lp_kernel(const ContractLpPr
       }
     }
   }
-
-  // Epilogue 2: partial weight of (row, branch, column tile); padded columns
-  // are exact zeros.  Fixed reduction order: lanes by xor butterfly, then the
-  // two column halves of the tile.
-  float* red = reinterpret_cast<float*>(lds);
-#pragma unroll
-  for (int rb = 0; rb < 2; ++rb) {
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      float s = 0.f;
-#pragma unroll
-      for (int cb = 0; cb < 4; ++cb) s += acc[rb][cb][v] * acc[rb][cb][v];
-#pragma unroll
-      for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off, 32);
-      if (j == 0) red[(wave & 1) * BM + wr + rb * 32 + (v >> 2) * 8 + half * 4 + (v & 3)] = s;
-    }
-  }
-  __syncthreads();
-  if (tid < BM) {
-    const int gr = m0 + tid;
-    if (gr < rows) a.qpart[(size_t)gr * (a.d * T_) + branch * T_ + ct] = red[tid] + red[BM + tid];
-  }
+  // Epilogue 2: partial weights per 32 complex columns; padded columns are
+  // exact zeros.
+  const int TP = a.CP / kPartCols;  // partials per branch
+  store_partials<NWC>(acc, reinterpret_cast<float*>(lds), wave, wr, half, j, tid, m0, rows, a.qpart,
+                      (size_t)a.d * TP, branch * TP + c0 / kPartCols);
 }
 
 // ------------------------------------------------------------ fp16f8 ----
@@ -475,12 +527,18 @@ __global__ __launch_bounds__(256) void pack_f16f8_kernel(const PackProb* probs, 
 // and the loads issued after the barrier of pair m+1 (slices 2m+5, 2m+6)
 // refill the two buffers of pair m, whose LDS reads every wave has finished
 // (LDS-read wait before the barrier).
-__global__ __launch_bounds__(NTHR, 1) void contract_f16f8_kernel(const ContractLpProb* probs, const int* tn_start,
-                                                                 int nprob, int tn_total, int tiles_m, int per_xcd,
-                                                                 int group_m, const ChunkArgs* chp) {
-  constexpr int NARR = 4;  // Lh, L8 (pair plane), Bh, B8 (pair plane)
-  constexpr int STAGE = NARR * ARR;
-  constexpr int IPW = NARR;
+// (The body is a device function template with one plain kernel per
+// variant below.)
+template <int NWC>
+__device__ inline void contract_f16f8_body(const ContractLpProb* probs, const int* tn_start, int nprob, int tn_total,
+                                           int tiles_m, int per_xcd, int group_m, const ChunkArgs* chp) {
+  typedef LpTile<NWC> Tile;
+  constexpr int NST = 5;  // the pair scheme below needs five slices
+  constexpr int BOFF = 2 * ARR;  // stage: Lh, L8 (pair plane), Bh, B8 (pair plane)
+  constexpr int STAGE = 2 * ARR + 2 * Tile::BARR;
+  constexpr int GROUPS = 2 * 8 + 2 * (Tile::BN / 32);
+  constexpr int IPW = GROUPS / (4 * NWC);
+  static_assert(GROUPS % (4 * NWC) == 0 && IPW <= 15, "loads must divide evenly; vmcnt immediates");
   __shared__ __attribute__((aligned(16))) char lds[NST * STAGE];
 
   int tm, tng;
@@ -489,23 +547,25 @@ __global__ __launch_bounds__(NTHR, 1) void contract_f16f8_kernel(const ContractL
   const int p = find_problem(tn_start, nprob, tng);
   const ContractLpProb a = probs[p];
   const int tn = tng - tn_start[p];
-  const int T_ = a.CP / kLpBNC;
-  const int branch = tn / T_;
-  const int ct = tn - branch * T_;
+  const int TC = a.CP / (Tile::BN / 2);  // column tiles per branch
+  const int branch = tn / TC;
+  const int ct = tn - branch * TC;
   const int m0 = tm * BM;
-  const int c0 = ct * kLpBNC;
-  const size_t cblk = ((size_t)branch * a.CP + c0) * 2 / BM;
+  const int c0 = ct * (Tile::BN / 2);
+  const size_t prow = ((size_t)branch * a.CP + c0) * 2;  // first packed row of the tile
+  const size_t cblk = prow >> 8;
+  const int crow = (int)(prow & 255);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wr = (wave >> 1) * 64;
-  const int wc = (wave & 1) * 128;
+  const int wr = (wave / NWC) * 64;
+  const int wc = (wave % NWC) * 128;
   const int half = lane >> 5;
   const int j = lane & 31;
 
   // Loads: planes and pair planes are addressed alike (8 KiB per 256 rows
-  // and 16 K).  Load i of a wave reads array q = (wave*IPW + i) / 8, a choice
+  // and 16 K).  Load i of a wave reads operand tile q (load_slot), a choice
   // that is uniform over the wave, through a buffer descriptor (scalar
   // registers) based at the tile's 256-row block; the slice is a scalar
   // offset and each lane keeps one 32-bit byte offset.
@@ -515,17 +575,17 @@ __global__ __launch_bounds__(NTHR, 1) void contract_f16f8_kernel(const ContractL
   int voff[IPW], ldst[IPW];
 #pragma unroll
   for (int i = 0; i < IPW; ++i) {
-    const int idx = wv * IPW + i;
-    const int q = idx >> 3, rg = idx & 7;  // q: 0 Lh, 1 L8, 2 Bh, 3 B8
+    int q, rg, dst;
+    load_slot<NWC>(wv * IPW + i, 2, q, rg, dst);  // q: 0 Lh, 1 L8, 2 Bh, 3 B8
     const char* base = q == 0 ? (const char*)a.Lh + (size_t)tm * kbs
                      : q == 1 ? (const char*)a.Ll + (size_t)tm * kbs
                      : q == 2 ? (const char*)a.Bh + cblk * kbs
                               : (const char*)a.Bl + cblk * kbs;
     rsrc[i] = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)0xFFFFFFFF, 0x00020000);
-    const int row = rg * 32 + (lane >> 1);
+    const int row = rg * 32 + (lane >> 1) + (q >= 2 ? crow : 0);
     const int lc = (lane & 1) ^ swz(row);
     voff[i] = row * 32 + lc * 16;
-    ldst[i] = q * ARR + rg * 1024;
+    ldst[i] = dst;
   }
   auto issue = [&](int kt) {
     char* st = lds + (kt % NST) * STAGE;
@@ -553,11 +613,11 @@ __global__ __launch_bounds__(NTHR, 1) void contract_f16f8_kernel(const ContractL
   // every row block, the blocks being 1 KiB apart (immediate offsets).
   const int sj = swz(j);
   const unsigned a_h = (unsigned)((wr + j) * 32 + ((half ^ sj) << 4));           // Lh, chunk `half`
-  const unsigned b_h = (unsigned)(2 * ARR + (wc + j) * 32 + ((half ^ sj) << 4));  // Bh, chunk `half`
+  const unsigned b_h = (unsigned)(BOFF + (wc + j) * 32 + ((half ^ sj) << 4));     // Bh, chunk `half`
   const unsigned a8_0 = (unsigned)(ARR + (wr + j) * 32 + (sj << 4));              // L8, chunk 0
   const unsigned a8_1 = (unsigned)(ARR + (wr + j) * 32 + ((1 ^ sj) << 4));        // L8, chunk 1
-  const unsigned b8_0 = (unsigned)(3 * ARR + (wc + j) * 32 + (sj << 4));          // B8, chunk 0
-  const unsigned b8_1 = (unsigned)(3 * ARR + (wc + j) * 32 + ((1 ^ sj) << 4));    // B8, chunk 1
+  const unsigned b8_0 = (unsigned)(BOFF + Tile::BARR + (wc + j) * 32 + (sj << 4));        // B8, chunk 0
+  const unsigned b8_1 = (unsigned)(BOFF + Tile::BARR + (wc + j) * 32 + ((1 ^ sj) << 4));  // B8, chunk 1
   auto read16 = [&](int kt, Ops16& o) {
     const char* st = lds + (kt % NST) * STAGE;
 #pragma unroll
@@ -662,24 +722,22 @@ __global__ __launch_bounds__(NTHR, 1) void contract_f16f8_kernel(const ContractL
       }
     }
   }
-  float* red = reinterpret_cast<float*>(lds);
-#pragma unroll
-  for (int rb = 0; rb < 2; ++rb) {
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      float s2 = 0.f;
-#pragma unroll
-      for (int cb = 0; cb < 4; ++cb) s2 += acc[rb][cb][v] * acc[rb][cb][v];
-#pragma unroll
-      for (int off = 16; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 32);
-      if (j == 0) red[(wave & 1) * BM + wr + rb * 32 + (v >> 2) * 8 + half * 4 + (v & 3)] = s2;
-    }
-  }
-  __syncthreads();
-  if (tid < BM) {
-    const int gr = m0 + tid;
-    if (gr < rows) a.qpart[(size_t)gr * (a.d * T_) + branch * T_ + ct] = red[tid] + red[BM + tid];
-  }
+  const int TP = a.CP / kPartCols;  // partials per branch
+  store_partials<NWC>(acc, reinterpret_cast<float*>(lds), wave, wr, half, j, tid, m0, rows, a.qpart,
+                      (size_t)a.d * TP, branch * TP + c0 / kPartCols);
+}
+
+__global__ __launch_bounds__(LpTile<2>::NTHR, 1) void contract_f16f8_wide(const ContractLpProb* probs,
+                                                                          const int* tn_start, int nprob, int tn_total,
+                                                                          int tiles_m, int per_xcd, int group_m,
+                                                                          const ChunkArgs* chp) {
+  contract_f16f8_body<2>(probs, tn_start, nprob, tn_total, tiles_m, per_xcd, group_m, chp);
+}
+__global__ __launch_bounds__(LpTile<1>::NTHR, 1) void contract_f16f8_narrow(const ContractLpProb* probs,
+                                                                            const int* tn_start, int nprob,
+                                                                            int tn_total, int tiles_m, int per_xcd,
+                                                                            int group_m, const ChunkArgs* chp) {
+  contract_f16f8_body<1>(probs, tn_start, nprob, tn_total, tiles_m, per_xcd, group_m, chp);
 }
 
 template <typename T, int NPROD>
@@ -689,16 +747,31 @@ hipError_t launch_pack_t(const PackProb* probs, const int* blk_start, int nprob,
   return hipGetLastError();
 }
 
+// Grid of a contraction launch: one workgroup per (row tile, column tile),
+// dealt to the XCDs in contiguous runs (tiling.h).  The kernel is named in
+// the launch itself so that its device code is instantiated.
+#define MPS_CONTRACT_LAUNCH(KERNEL, NTHREADS)                                                                 \
+  do {                                                                                                        \
+    const int tiles_m = (grid_rows + BM - 1) / BM;                                                            \
+    const long long ntiles = (long long)tiles_m * tn_total;                                                   \
+    if (ntiles <= 0 || nprob <= 0) return hipSuccess;                                                         \
+    const int per_xcd = (int)((ntiles + 7) / 8);                                                              \
+    hipLaunchKernelGGL(KERNEL, dim3(per_xcd * 8), dim3(NTHREADS), 0, s, probs, tn_start, nprob, tn_total, tiles_m, \
+                       per_xcd, group_m, ch);                                                                 \
+    return hipGetLastError();                                                                                 \
+  } while (0)
+
 template <typename T, int NPROD>
-hipError_t launch_contract_t(const ContractLpProb* probs, const int* tn_start, int nprob, int tn_total,
+hipError_t launch_contract_t(int tile, const ContractLpProb* probs, const int* tn_start, int nprob, int tn_total,
                              const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s) {
-  const int tiles_m = (grid_rows + BM - 1) / BM;
-  const long long ntiles = (long long)tiles_m * tn_total;
-  if (ntiles <= 0 || nprob <= 0) return hipSuccess;
-  const int per_xcd = (int)((ntiles + 7) / 8);
-  hipLaunchKernelGGL((contract_lp_kernel<T, NPROD>), dim3(per_xcd * 8), dim3(NTHR), 0, s, probs, tn_start, nprob,
-                     tn_total, tiles_m, per_xcd, group_m, ch);
-  return hipGetLastError();
+  if (tile == kTileNarrow) MPS_CONTRACT_LAUNCH((contract_lp_kernel<T, NPROD, 1>), LpTile<1>::NTHR);
+  MPS_CONTRACT_LAUNCH((contract_lp_kernel<T, NPROD, 2>), LpTile<2>::NTHR);
+}
+
+hipError_t launch_f16f8(int tile, const ContractLpProb* probs, const int* tn_start, int nprob, int tn_total,
+                        const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s) {
+  if (tile == kTileNarrow) MPS_CONTRACT_LAUNCH(contract_f16f8_narrow, LpTile<1>::NTHR);
+  MPS_CONTRACT_LAUNCH(contract_f16f8_wide, LpTile<2>::NTHR);
 }
 
 }  // namespace
@@ -721,24 +794,16 @@ hipError_t launch_pack_lp(int form, const PackProb* probs, const int* blk_start,
   return launch_pack_t<f16_t, 1>(probs, blk_start, nprob, blk_total, s);  // kFp16, kFp16x2: high parts only
 }
 
-hipError_t launch_contract_lp(int form, const ContractLpProb* probs, const int* tn_start, int nprob, int tn_total,
-                              const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s) {
-  if (form == kFp16F8) {
-    const int tiles_m = (grid_rows + BM - 1) / BM;
-    const long long ntiles = (long long)tiles_m * tn_total;
-    if (ntiles <= 0 || nprob <= 0) return hipSuccess;
-    const int per_xcd = (int)((ntiles + 7) / 8);
-    hipLaunchKernelGGL(contract_f16f8_kernel, dim3(per_xcd * 8), dim3(NTHR), 0, s, probs, tn_start, nprob, tn_total,
-                       tiles_m, per_xcd, group_m, ch);
-    return hipGetLastError();
-  }
+hipError_t launch_contract_lp(int form, int tile, const ContractLpProb* probs, const int* tn_start, int nprob,
+                              int tn_total, const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s) {
+  if (form == kFp16F8) return launch_f16f8(tile, probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s);
   if (form == kBf16x3)
-    return launch_contract_t<bf16_t, 3>(probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s);
+    return launch_contract_t<bf16_t, 3>(tile, probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s);
   if (form == kFp16x3)
-    return launch_contract_t<f16_t, 3>(probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s);
+    return launch_contract_t<f16_t, 3>(tile, probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s);
   if (form == kFp16x2)
-    return launch_contract_t<f16_t, 2>(probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s);
-  return launch_contract_t<f16_t, 1>(probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s);
+    return launch_contract_t<f16_t, 2>(tile, probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s);
+  return launch_contract_t<f16_t, 1>(tile, probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s);
 }
 
 }  // namespace mps

@@ -604,6 +604,24 @@ __global__ void init_f16f8_kernel(const InitProb* probs, const ChunkArgs* chp) {
   }
 }
 
+// Operand-sized noise for the tile autotuner's timing launches: values of
+// the magnitude the sweep's operands have (a hash of the index; the timed
+// results are discarded).  kind 0: floats in +-0.05; 1: bf16; 2: fp16, both
+// in +-0.05; 3: finite E4M3 codes.
+__global__ void fill_noise_kernel(void* p, size_t n, int kind, unsigned seed) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    unsigned x = (unsigned)i * 2654435761u ^ (unsigned)(i >> 32) ^ seed;
+    x ^= x >> 15;
+    x *= 0x2c1b3c6du;
+    x ^= x >> 12;
+    const float v = ((float)(x & 0xFFFF) * (1.f / 65536.f) - 0.5f) * 0.1f;
+    if (kind == 0) ((float*)p)[i] = v;
+    else if (kind == 1) ((bf16_t*)p)[i] = (bf16_t)v;
+    else if (kind == 2) ((f16_t*)p)[i] = (f16_t)v;
+    else ((unsigned char*)p)[i] = (unsigned char)((x >> 16) & 0x7E);
+  }
+}
+
 __global__ void zero_int_kernel(int* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
@@ -627,6 +645,12 @@ hipError_t launch_init(int form, const InitProb* probs, int nprob, const ChunkAr
     else
       hipLaunchKernelGGL(init_lp_kernel<f16_t>, grid, dim3(256), 0, s, probs, ch);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_noise(void* p, size_t n, int kind, unsigned seed, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_noise_kernel, dim3(2048), dim3(256), 0, s, p, n, kind, seed);
   return hipGetLastError();
 }
 

@@ -32,6 +32,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -211,12 +212,14 @@ int validate_chain(const Chain& c, int precision, Shape& sh, int idx) {
     if (!c.tensors[k]) return fail(MPS_EINVAL, "chain %d: tensors[%d] is NULL", idx, k);
     sh.wmax = std::max<int64_t>(sh.wmax, (int64_t)c.d[k] * c.chi[k + 1]);
     if (lowp) {
-      const int CP = mps::lp_pad_cols(c.chi[k + 1]);
-      sh.qtmax = std::max<int64_t>(sh.qtmax, (int64_t)c.d[k] * (CP / mps::kLpBNC));
-      sh.bmax = std::max<int64_t>(sh.bmax, (int64_t)c.d[k] * CP * 2 * mps::lp_pad_k(c.chi[k]));
+      // the wide variant's padding is the larger one
+      const int CP = mps::lp_pad_cols(c.chi[k + 1], mps::kTileWide);
+      sh.qtmax = std::max<int64_t>(sh.qtmax, (int64_t)c.d[k] * (CP / mps::kPartCols));
+      const int64_t prow = ((int64_t)c.d[k] * CP * 2 + 255) / 256 * 256;
+      sh.bmax = std::max<int64_t>(sh.bmax, prow * mps::lp_pad_k(c.chi[k]));
       sh.csmax = std::max<int64_t>(sh.csmax, (int64_t)c.d[k] * CP);
     } else {
-      sh.qtmax = std::max<int64_t>(sh.qtmax, (int64_t)c.d[k] * mps::col_tiles(c.chi[k + 1]));
+      sh.qtmax = std::max<int64_t>(sh.qtmax, (int64_t)c.d[k] * mps::fp32_parts(c.chi[k + 1]));
     }
   }
   return MPS_OK;
@@ -236,11 +239,15 @@ struct Tables {
 
 struct Step {
   int nprob = 0;
-  int tn_total = 0;   // contraction column tiles over all problems of the step
+  // contraction problems of the step by tile variant (wide, narrow): count,
+  // column tiles over them, and their tables
+  int ncp[2] = {0, 0};
+  int tn_tot[2] = {0, 0};
+  size_t ctab[2] = {0, 0}, tntab[2] = {0, 0};
   int blk_total = 0;  // packing blocks over all problems of the step
   int cm_total = 0;   // column-scale blocks (MPS_FP16F8)
   int meas_rpw = 64;  // samples per wave in the measurement (set by the largest chi_r)
-  size_t contract = 0, tn_start = 0, pack = 0, blk_start = 0, measure = 0, cm_start = 0;  // offsets in the table blob
+  size_t pack = 0, blk_start = 0, measure = 0, cm_start = 0;  // offsets in the table blob
   double flops_per_row = 0, meas_bytes_per_row = 0;
 };
 
@@ -259,9 +266,28 @@ struct mps_ctx {
   hipEvent_t ev_expand[2] = {nullptr, nullptr};
   std::vector<hipEvent_t> events;
   mps_stats st{};
+  // contraction tile per site shape (chi_l, d, chi_r, rows per launch), set by
+  // mps_autotune_tiles or mps_set_tiles; shapes not listed take the wide tile
+  std::map<std::array<int64_t, 4>, int> tiles;
 };
 
 namespace {
+
+// Contraction tile of a site shape at `rows` samples per launch.
+int tile_for(const mps_ctx* h, int K, int d, int chi_r, int64_t rows) {
+  const auto it = h->tiles.find({(int64_t)K, (int64_t)d, (int64_t)chi_r, rows});
+  return it == h->tiles.end() ? (int)mps::kTileWide : it->second;
+}
+
+// Whether a chain goes through the persistent small-bond kernel (see
+// run_sweep); such chains never use the per-site contraction.
+bool small_chain(const mps_options& o, const int32_t* chi, const int32_t* d, int M) {
+  if (o.fused_small != 0) return false;
+  int cmax = 0, dmax = 0;
+  for (int k = 0; k <= M; ++k) cmax = std::max(cmax, (int)chi[k]);
+  for (int k = 0; k < M; ++k) dmax = std::max(dmax, (int)d[k]);
+  return cmax <= mps::kSmallChi && dmax <= mps::kSmallD;
+}
 
 // Whether a complex-fp8 site in host memory can be expanded to values that
 // are exact in fp16: every block scale a power of two 2^e, the exponents
@@ -488,8 +514,8 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
     size_t t = 0;
     for (const Chain& c : chains)
       t += (size_t)c.M * (sizeof(mps::ContractProb) + sizeof(mps::ContractLpProb) + sizeof(mps::PackProb) +
-                          sizeof(mps::MeasureProb) + 3 * sizeof(int));
-    t += (size_t)B * sizeof(mps::InitProb) + (size_t)Mmax * 8 * 256 + 4096;
+                          sizeof(mps::MeasureProb) + 4 * sizeof(int));
+    t += (size_t)B * sizeof(mps::InitProb) + (size_t)Mmax * 10 * 256 + 4096;
     return t * (size_t)nstate + (size_t)nstate * sizeof(mps::ChunkArgs) + 512 + small_bytes;
   };
   auto scratch_for = [&](int64_t rows, std::vector<ChainBufs>* bufs) -> size_t {
@@ -584,20 +610,21 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
     }
     init_off[s] = tab.put(init);
     for (int k = 0; k < Mmax; ++k) {
-      std::vector<mps::ContractProb> cf;
-      std::vector<mps::ContractLpProb> cl;
+      std::vector<mps::ContractProb> cf[2];
+      std::vector<mps::ContractLpProb> cl[2];
       std::vector<mps::PackProb> pk;
       std::vector<mps::MeasureProb> ms;
-      std::vector<int> tns(1, 0), blks(1, 0), cms(1, 0);
+      std::vector<int> tns[2] = {std::vector<int>(1, 0), std::vector<int>(1, 0)}, blks(1, 0), cms(1, 0);
       Step& sp = steps[(size_t)s * Mmax + k];
       for (int b = 0; b < B; ++b) {
         const Chain& c = chains[b];
         if (k >= c.M) continue;
         const int K = c.chi[k], dk = c.d[k], chr = c.chi[k + 1];
+        const int tile = tile_for(h, K, dk, chr, nc);
         int T;
         if (lowp) {
-          const int CP = mps::lp_pad_cols(chr), Kp = mps::lp_pad_k(K);
-          T = CP / mps::kLpBNC;
+          const int CP = mps::lp_pad_cols(chr, tile), Kp = mps::lp_pad_k(K);
+          T = CP / mps::kPartCols;
           const bool f8 = o.precision == MPS_FP16F8;
           float* cs = f8 ? (float*)at(bufs[b].colscale) : nullptr;
           mps::PackProb pp{site_A(b, k), at(bufs[b].Bh), split ? at(bufs[b].Bl) : nullptr, K, dk, chr, CP, Kp, cs,
@@ -607,14 +634,15 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
           cms.push_back(cms.back() + mps::colmax_blocks(K) * (CP / 64) * dk);
           mps::ContractLpProb cp{sat(b, bufs[b].Lh), split ? sat(b, bufs[b].Ll) : nullptr, pp.Bh, pp.Bl,
                                  (float2*)at(bufs[b].W), (float*)at(bufs[b].qpart), Kp, dk, chr, CP, cs};
-          cl.push_back(cp);
+          cl[tile].push_back(cp);
+          tns[tile].push_back(tns[tile].back() + dk * mps::lp_col_tiles(CP, tile));
         } else {
-          T = mps::col_tiles(chr);
+          T = mps::fp32_parts(chr);
           mps::ContractProb cp{(const float2*)sat(b, bufs[b].L), site_A(b, k), (float2*)at(bufs[b].W),
                                (float*)at(bufs[b].qpart), K, dk, chr};
-          cf.push_back(cp);
+          cf[tile].push_back(cp);
+          tns[tile].push_back(tns[tile].back() + dk * mps::col_tiles(chr));
         }
-        tns.push_back(tns.back() + dk * T);
         mps::MeasureProb mp{};
         mp.W = (const float2*)at(bufs[b].W);
         mp.qpart = (const float*)at(bufs[b].qpart);
@@ -645,11 +673,14 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
         sp.meas_bytes_per_row += (double)dk * T * 4 + 2.0 * chr * 8 + 4 + 16;
       }
       sp.nprob = (int)ms.size();
-      sp.tn_total = tns.back();
+      for (int v = 0; v < 2; ++v) {
+        sp.ncp[v] = lowp ? (int)cl[v].size() : (int)cf[v].size();
+        sp.tn_tot[v] = tns[v].back();
+        sp.ctab[v] = lowp ? tab.put(cl[v]) : tab.put(cf[v]);
+        sp.tntab[v] = tab.put(tns[v]);
+      }
       sp.blk_total = blks.back();
       sp.cm_total = cms.back();
-      sp.contract = lowp ? tab.put(cl) : tab.put(cf);
-      sp.tn_start = tab.put(tns);
       sp.pack = tab.put(pk);
       sp.blk_start = tab.put(blks);
       sp.cm_start = tab.put(cms);
@@ -764,13 +795,17 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
   auto run_site = [&](int64_t s, int k, const mps::ChunkArgs* ch, int grid_rows) -> int {
     const Step& sp = steps[(size_t)s * Mmax + k];
     MPS_TRY(mark(k, 2, stream));
-    if (lowp)
-      e = mps::launch_contract_lp(site_form(k), (const mps::ContractLpProb*)tp(sp.contract), (const int*)tp(sp.tn_start),
-                                  sp.nprob, sp.tn_total, ch, grid_rows, group, stream);
-    else
-      e = mps::launch_contract_f32((const mps::ContractProb*)tp(sp.contract), (const int*)tp(sp.tn_start), sp.nprob,
-                                   sp.tn_total, ch, grid_rows, group, stream);
-    if (e != hipSuccess) return hip_fail(e, "contraction launch");
+    for (int v = 0; v < 2; ++v) {
+      if (sp.ncp[v] == 0) continue;
+      if (lowp)
+        e = mps::launch_contract_lp(site_form(k), v, (const mps::ContractLpProb*)tp(sp.ctab[v]),
+                                    (const int*)tp(sp.tntab[v]), sp.ncp[v], sp.tn_tot[v], ch, grid_rows, group,
+                                    stream);
+      else
+        e = mps::launch_contract_f32(v, (const mps::ContractProb*)tp(sp.ctab[v]), (const int*)tp(sp.tntab[v]),
+                                     sp.ncp[v], sp.tn_tot[v], ch, grid_rows, group, stream);
+      if (e != hipSuccess) return hip_fail(e, "contraction launch");
+    }
     MPS_TRY(mark(k, 3, stream));
     MPS_TRY(mark(k, 4, stream));
     MPS_HIP(mps::launch_measure(form, (const mps::MeasureProb*)tp(sp.measure), sp.nprob, ch, grid_rows, seed, nflag,
@@ -836,7 +871,7 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
   auto count = [&](int k, int rows, bool pack) {
     const Step& sp = steps[k];
     st.pack_launches += (lowp && pack) ? 1 : 0;
-    st.contract_launches++;
+    st.contract_launches += (sp.ncp[0] > 0) + (sp.ncp[1] > 0);
     st.measure_launches++;
     st.contract_flops += sp.flops_per_row * rows;
     st.measure_bytes += sp.meas_bytes_per_row * rows;
@@ -1207,6 +1242,196 @@ int mps_autotune(mps_handle h, const void* const* tensors, int32_t dtype, const 
   r.tile_group = best_g;
   r.rate = best;
   *rep = r;
+  g_err.clear();
+  return MPS_OK;
+}
+
+int mps_set_tiles(mps_handle h, const mps_tile_choice* choices, int32_t n) {
+  if (!h) return fail(MPS_EINVAL, "handle is NULL");
+  if (n < 0) return fail(MPS_EINVAL, "n = %d < 0", n);
+  if (n == 0) {
+    h->tiles.clear();
+    return MPS_OK;
+  }
+  if (!choices) return fail(MPS_EINVAL, "choices is NULL");
+  for (int i = 0; i < n; ++i) {
+    const mps_tile_choice& c = choices[i];
+    if (c.chi_l < 1 || c.chi_l > kMaxChi || c.chi_r < 1 || c.chi_r > kMaxChi || c.d < 1 || c.d > kMaxD ||
+        c.rows < 1 || (c.tile != MPS_TILE_WIDE && c.tile != MPS_TILE_NARROW))
+      return fail(MPS_EINVAL, "choice %d: shape (%d, %d, %d), rows %lld or tile %d out of range", i, c.chi_l, c.d,
+                  c.chi_r, (long long)c.rows, c.tile);
+  }
+  for (int i = 0; i < n; ++i) {
+    const mps_tile_choice& c = choices[i];
+    h->tiles[{(int64_t)c.chi_l, (int64_t)c.d, (int64_t)c.chi_r, c.rows}] = c.tile;
+  }
+  return MPS_OK;
+}
+
+int mps_autotune_tiles(mps_handle h, int32_t B, const mps_chain* chains_in, int64_t rows, uint64_t seed,
+                       mps_tile_choice* out, int32_t cap, int32_t* n_out) {
+  if (!h) return fail(MPS_EINVAL, "handle is NULL");
+  if (B < 1 || B > kMaxChains) return fail(MPS_EINVAL, "B = %d out of [1, %d]", B, kMaxChains);
+  if (!chains_in) return fail(MPS_EINVAL, "chains is NULL");
+  if (rows < 1 || rows > ((int64_t)1 << 30)) return fail(MPS_EINVAL, "rows = %lld out of [1, 2^30]", (long long)rows);
+  if (cap < 0 || (cap > 0 && !out)) return fail(MPS_EINVAL, "out / cap");
+  const mps_options& o = h->opt;
+  const bool lowp = o.precision != MPS_FP32;
+  const int form = lowp ? lp_form(o.precision) : 0;
+  // distinct shapes of the chains that take per-site launches, each with one
+  // of its site tensors (packed for the timing launches)
+  std::map<std::array<int, 3>, const void*> shapes;
+  Shape all;
+  for (int b = 0; b < B; ++b) {
+    const mps_chain& c = chains_in[b];
+    Chain ch{c.tensors, c.chi, c.d, c.M, c.mps_id, nullptr, nullptr, Shape{}};
+    int rc = validate_chain(ch, o.precision, ch.sh, b);
+    if (rc) return rc;
+    if (small_chain(o, c.chi, c.d, c.M)) continue;
+    all.chimax = std::max(all.chimax, ch.sh.chimax);
+    all.wmax = std::max(all.wmax, ch.sh.wmax);
+    all.qtmax = std::max(all.qtmax, ch.sh.qtmax);
+    all.kpmax = std::max(all.kpmax, ch.sh.kpmax);
+    all.bmax = std::max(all.bmax, ch.sh.bmax);
+    all.csmax = std::max(all.csmax, ch.sh.csmax);
+    for (int k = 0; k < c.M; ++k) shapes.emplace(std::array<int, 3>{c.chi[k], c.d[k], c.chi[k + 1]}, c.tensors[k]);
+  }
+  if (n_out) *n_out = (int32_t)shapes.size();
+  if (shapes.empty()) return MPS_OK;
+
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev == 0) return fail(MPS_ENODEV, "no HIP device available");
+  if (h->device >= ndev) return fail(MPS_ENODEV, "device %d not present (%d devices)", h->device, ndev);
+  if ((e = hipSetDevice(h->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  PtrClassifier where;
+  for (const auto& kv : shapes) {
+    const PtrClass pc = where.classify(kv.second);
+    if (pc.type != hipMemoryTypeDevice || pc.device != h->device)
+      return fail(MPS_EINVAL, "site tensors must be device-resident complex64 on device %d", h->device);
+    if (pc.room < (size_t)kv.first[0] * kv.first[1] * kv.first[2] * sizeof(float2))
+      return fail(MPS_EINVAL, "a site tensor of shape (%d, %d, %d) runs past the end of its allocation", kv.first[0],
+                  kv.first[1], kv.first[2]);
+  }
+
+  // scratch of the timing launches, freed before returning
+  const size_t ra = (size_t)((rows + mps::kLpBM - 1) / mps::kLpBM * mps::kLpBM);
+  size_t sz[8] = {0};
+  enum { S_L, S_LL, S_BH, S_BL, S_W, S_Q, S_CS, S_TAB };
+  sz[S_L] = lowp ? ra * all.kpmax * 2 : (size_t)rows * all.chimax * sizeof(float2);
+  sz[S_LL] = lowp && is_split(o.precision) ? ra * all.kpmax * 2 : 0;
+  sz[S_BH] = lowp ? (size_t)all.bmax * 2 : 0;
+  sz[S_BL] = lowp && is_split(o.precision) ? (size_t)all.bmax * 2 : 0;
+  sz[S_W] = (size_t)rows * all.wmax * sizeof(float2);
+  sz[S_Q] = (size_t)rows * all.qtmax * sizeof(float);
+  sz[S_CS] = form == mps::kFp16F8 ? (size_t)all.csmax * 17 * sizeof(float) : 0;
+  sz[S_TAB] = 4096;
+  size_t total = 0, off[8];
+  for (int i = 0; i < 8; ++i) {
+    off[i] = total;
+    total += align_up(sz[i]);
+  }
+  char* buf = nullptr;
+  if ((e = hipMalloc((void**)&buf, total)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MPS_ENOMEM, "autotune: timing scratch of %zu B does not fit", total);
+  }
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int err = MPS_OK;
+  auto cleanup = [&]() {
+    (void)hipDeviceSynchronize();
+    for (hipEvent_t x : ev)
+      if (x) (void)hipEventDestroy(x);
+    (void)hipFree(buf);
+  };
+  auto chk = [&](hipError_t x, const char* what) {
+    if (x != hipSuccess && err == MPS_OK) err = hip_fail(x, what);
+    return err == MPS_OK;
+  };
+  hipStream_t stream = (hipStream_t)o.stream;
+  const int group = o.tile_group > 0 ? o.tile_group : kDefaultGroup;
+  chk(hipEventCreate(&ev[0]), "hipEventCreate") && chk(hipEventCreate(&ev[1]), "hipEventCreate");
+  // operand noise of the sweep's magnitudes (the timed outputs are discarded)
+  const int lkind = !lowp ? 0 : form == mps::kBf16x3 ? 1 : 2;
+  if (err == MPS_OK) chk(mps::launch_fill_noise(buf + off[S_L], lowp ? sz[S_L] / 2 : sz[S_L] / 4, lkind, 1, stream), "noise");
+  if (err == MPS_OK && sz[S_LL])
+    chk(mps::launch_fill_noise(buf + off[S_LL], form == mps::kFp16F8 ? sz[S_LL] : sz[S_LL] / 2,
+                               form == mps::kFp16F8 ? 3 : lkind, 2, stream),
+        "noise");
+  char* const tabd = buf + off[S_TAB];
+  const mps::ChunkArgs ca{(int)rows, 0, 0, 0};
+  constexpr int kReps = 3;
+  int idx = 0;
+  for (const auto& kv : shapes) {
+    if (err != MPS_OK) break;
+    const int K = kv.first[0], dk = kv.first[1], chr = kv.first[2];
+    double ms[2] = {0.0, 0.0};
+    for (int v = 0; v < 2 && err == MPS_OK; ++v) {
+      // one problem: tables, then (16-bit forms) packing of the real tensor
+      std::vector<char> blob(4096, 0);
+      auto put = [&](size_t at, const void* p, size_t n) { std::memcpy(blob.data() + at, p, n); };
+      int tn_total = 0;
+      if (lowp) {
+        const int CP = mps::lp_pad_cols(chr, v), Kp = mps::lp_pad_k(K);
+        float* cs = form == mps::kFp16F8 ? (float*)(buf + off[S_CS]) : nullptr;
+        mps::PackProb pp{(const float2*)kv.second, buf + off[S_BH], sz[S_BL] ? buf + off[S_BL] : nullptr,
+                         K, dk, chr, CP, Kp, cs, cs ? cs + all.csmax : nullptr};
+        mps::ContractLpProb cp{buf + off[S_L], sz[S_LL] ? buf + off[S_LL] : nullptr, pp.Bh, pp.Bl,
+                               (float2*)(buf + off[S_W]), (float*)(buf + off[S_Q]), Kp, dk, chr, CP, cs};
+        tn_total = dk * mps::lp_col_tiles(CP, v);
+        const int blk[2] = {0, (CP / 64) * (Kp / 64) * dk}, cm[2] = {0, mps::colmax_blocks(K) * (CP / 64) * dk};
+        const int tn[2] = {0, tn_total};
+        put(0, &cp, sizeof cp);
+        put(512, &pp, sizeof pp);
+        put(1024, tn, sizeof tn);
+        put(1040, blk, sizeof blk);
+        put(1056, cm, sizeof cm);
+        put(1088, &ca, sizeof ca);
+        if (!chk(hipMemcpyAsync(tabd, blob.data(), blob.size(), hipMemcpyHostToDevice, stream), "hipMemcpyAsync")) break;
+        if (form == mps::kFp16F8 &&
+            !chk(mps::launch_colscale((const mps::PackProb*)(tabd + 512), (const int*)(tabd + 1056), 1, cm[1], stream),
+                 "column-scale launch"))
+          break;
+        if (!chk(mps::launch_pack_lp(form, (const mps::PackProb*)(tabd + 512), (const int*)(tabd + 1040), 1, blk[1],
+                                     stream),
+                 "pack launch"))
+          break;
+      } else {
+        mps::ContractProb cp{(const float2*)(buf + off[S_L]), (const float2*)kv.second, (float2*)(buf + off[S_W]),
+                             (float*)(buf + off[S_Q]), K, dk, chr};
+        tn_total = dk * mps::col_tiles(chr);
+        const int tn[2] = {0, tn_total};
+        put(0, &cp, sizeof cp);
+        put(1024, tn, sizeof tn);
+        put(1088, &ca, sizeof ca);
+        if (!chk(hipMemcpyAsync(tabd, blob.data(), blob.size(), hipMemcpyHostToDevice, stream), "hipMemcpyAsync")) break;
+      }
+      auto launch = [&]() {
+        return lowp ? mps::launch_contract_lp(form, v, (const mps::ContractLpProb*)tabd, (const int*)(tabd + 1024), 1,
+                                              tn_total, (const mps::ChunkArgs*)(tabd + 1088), (int)rows, group, stream)
+                    : mps::launch_contract_f32(v, (const mps::ContractProb*)tabd, (const int*)(tabd + 1024), 1,
+                                               tn_total, (const mps::ChunkArgs*)(tabd + 1088), (int)rows, group,
+                                               stream);
+      };
+      if (!chk(launch(), "contraction launch") || !chk(hipEventRecord(ev[0], stream), "hipEventRecord")) break;
+      for (int r = 0; r < kReps && err == MPS_OK; ++r) chk(launch(), "contraction launch");
+      if (err != MPS_OK || !chk(hipEventRecord(ev[1], stream), "hipEventRecord") ||
+          !chk(hipEventSynchronize(ev[1]), "hipEventSynchronize"))
+        break;
+      float t = 0.f;
+      if (!chk(hipEventElapsedTime(&t, ev[0], ev[1]), "hipEventElapsedTime")) break;
+      ms[v] = t / kReps;
+    }
+    if (err != MPS_OK) break;
+    // the wide tile unless the narrow one is clearly faster
+    const int tile = ms[1] < ms[0] * (1.0 - kTuneMargin) ? (int)mps::kTileNarrow : (int)mps::kTileWide;
+    h->tiles[{(int64_t)K, (int64_t)dk, (int64_t)chr, rows}] = tile;
+    if (idx < cap) out[idx] = mps_tile_choice{K, dk, chr, tile, rows, ms[0], ms[1]};
+    ++idx;
+  }
+  cleanup();
+  (void)seed;
+  if (err != MPS_OK) return err;
   g_err.clear();
   return MPS_OK;
 }

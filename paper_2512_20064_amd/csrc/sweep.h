@@ -21,16 +21,33 @@ constexpr int kBNC = 64;
 constexpr int kBK = 16;
 __host__ __device__ inline int col_tiles(int chi_r) { return (chi_r + kBNC - 1) / kBNC; }
 
-// ---- 16-bit contraction tile: kLpBM samples x kLpBNC complex columns of one
-// branch; K in stages of kLpBK real values.  The packed site tensor pads
-// every branch to a multiple of kLpBNC columns and K to a multiple of kLpKA
-// real values, with zeros.
+// ---- Contraction tile variants.  Each form has two tile shapes; both give
+// the same bits (same K order per output, same partial-weight granularity),
+// so the choice per site shape is free (the autotuner makes it):
+//   FP32    wide 128 x 64 (rows x complex columns, 4 waves), narrow 64 x 64
+//           (2 waves);
+//   16-bit  wide 256 x 128 (8 waves), narrow 256 x 64 (4 waves).
+enum TileVariant { kTileWide = 0, kTileNarrow = 1 };
+// Partial branch weights: one per row, branch and 32 complex columns, in
+// every kernel and variant (the measurement sums them in FP64 in order).
+constexpr int kPartCols = 32;
+__host__ __device__ inline int fp32_parts(int chi_r) { return 2 * col_tiles(chi_r); }
+
+// ---- 16-bit contraction tile: kLpBM samples x kLpBNC (wide) or kLpBNC/2
+// (narrow) complex columns of one branch; K in stages of kLpBK real values.
+// The packed site tensor pads every branch to a multiple of the variant's
+// column tile and K to a multiple of kLpKA real values, with zeros; its rows
+// are allocated in whole 256-row blocks.
 constexpr int kLpBM = 256;
 constexpr int kLpBNC = 128;
 constexpr int kLpBK = 16;
 constexpr int kLpKA = 64;
-__host__ __device__ inline int lp_pad_cols(int chi_r) { return (chi_r + kLpBNC - 1) / kLpBNC * kLpBNC; }
+__host__ __device__ inline int lp_pad_cols(int chi_r, int tile = kTileWide) {
+  const int w = tile == kTileNarrow ? kLpBNC / 2 : kLpBNC;
+  return (chi_r + w - 1) / w * w;
+}
 __host__ __device__ inline int lp_pad_k(int chi) { return (2 * chi + kLpKA - 1) / kLpKA * kLpKA; }
+__host__ __device__ inline int lp_col_tiles(int CP, int tile) { return CP / (tile == kTileNarrow ? kLpBNC / 2 : kLpBNC); }
 
 // Both 16-bit operands (left vectors, packed site tensor) are stored K-blocked:
 // a matrix of R rows (a multiple of 256) and Kp columns (a multiple of 16) is
@@ -96,7 +113,7 @@ struct ContractProb {
   const float2* L;   // [rows][K] complex, row pitch K
   const float2* A;   // [K][d][chi_r] complex (the site tensor)
   float2* W;         // [rows][d*chi_r] complex
-  float* qpart;      // [rows][d*T] partial branch weights, T = col_tiles(chi_r)
+  float* qpart;      // [rows][d*T] partial branch weights, T = fp32_parts(chi_r)
   int K, d, chi_r;
 };
 
@@ -117,7 +134,7 @@ struct ContractLpProb {
   const void* Bh;    // packed site tensor
   const void* Bl;
   float2* W;         // [rows][d*chi_r] complex FP32
-  float* qpart;      // [rows][d*T], T = CP / kLpBNC
+  float* qpart;      // [rows][d*T], T = CP / kPartCols
   int Kp, d, chi_r, CP;
   const float* colscale;  // kFp16F8: [d*CP] column scales s_c
 };
@@ -188,9 +205,11 @@ size_t stored_bytes(int kind, int chi_l, int d, int chi_r);
 hipError_t launch_decompress(const DecompressProb& p, hipStream_t s);
 
 hipError_t launch_zero_int(int* p, int n, hipStream_t s);
+// n elements of noise of kind 0 (float), 1 (bf16), 2 (fp16), 3 (E4M3 code)
+hipError_t launch_fill_noise(void* p, size_t n, int kind, unsigned seed, hipStream_t s);
 // form: 0 = FP32 path, kBf16x3, kFp16
 hipError_t launch_init(int form, const InitProb* probs, int nprob, const ChunkArgs* ch, int grid_rows, hipStream_t s);
-hipError_t launch_contract_f32(const ContractProb* probs, const int* tn_start, int nprob, int tn_total,
+hipError_t launch_contract_f32(int tile, const ContractProb* probs, const int* tn_start, int nprob, int tn_total,
                                const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s);
 hipError_t launch_pack_lp(int form, const PackProb* probs, const int* blk_start, int nprob, int blk_total,
                           hipStream_t s);
@@ -199,8 +218,10 @@ hipError_t launch_pack_lp(int form, const PackProb* probs, const int* blk_start,
 // (row block, branch, 64 complex columns), cm_start[p] = first workgroup of
 // problem p (nprob + 1 entries).
 hipError_t launch_colscale(const PackProb* probs, const int* cm_start, int nprob, int cm_total, hipStream_t s);
-hipError_t launch_contract_lp(int form, const ContractLpProb* probs, const int* tn_start, int nprob, int tn_total,
-                              const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s);
+// tile: kTileWide or kTileNarrow; every problem of the launch must have been
+// packed (CP) and tiled (tn_start) for that variant.
+hipError_t launch_contract_lp(int form, int tile, const ContractLpProb* probs, const int* tn_start, int nprob,
+                              int tn_total, const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s);
 // displaced: the problems carry per-sample displacements (MeasureProb::mu);
 // rows_per_wave: 64 / meas_lanes(largest chi_r of the problems) (kept for
 // callers; the measurement now sizes its lane groups per problem).

@@ -26,7 +26,9 @@ STATUS_NAMES = {0: "MPS_OK", -1: "MPS_EINVAL", -2: "MPS_ENOMEM", -3: "MPS_ENODEV
                 -4: "MPS_EHIP", -5: "MPS_ENUMERIC"}
 
 EXPORTS = ("mps_options_init", "mps_create", "mps_set_options", "mps_sample", "mps_sample_noalloc",
-           "mps_sample_batch", "mps_autotune", "mps_get_stats", "mps_last_error", "mps_destroy")
+           "mps_sample_batch", "mps_autotune", "mps_autotune_tiles", "mps_set_tiles", "mps_get_stats",
+           "mps_last_error", "mps_destroy")
+MPS_TILE_WIDE, MPS_TILE_NARROW = 0, 1
 NOALLOC_SCRATCH_BYTES = 256 << 20
 
 
@@ -121,6 +123,18 @@ class mps_tune_report(ctypes.Structure):
     ]
 
 
+class mps_tile_choice(ctypes.Structure):
+    _fields_ = [
+        ("chi_l", ctypes.c_int32),
+        ("d", ctypes.c_int32),
+        ("chi_r", ctypes.c_int32),
+        ("tile", ctypes.c_int32),
+        ("rows", ctypes.c_int64),
+        ("ms_wide", ctypes.c_double),
+        ("ms_narrow", ctypes.c_double),
+    ]
+
+
 class MPSError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
@@ -158,6 +172,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                  ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
                                  ctypes.POINTER(mps_tune_report)]
     lib.mps_autotune.restype = ctypes.c_int
+    lib.mps_autotune_tiles.argtypes = [P, ctypes.c_int32, ctypes.POINTER(mps_chain), ctypes.c_int64, ctypes.c_uint64,
+                                       ctypes.POINTER(mps_tile_choice), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.mps_autotune_tiles.restype = ctypes.c_int
+    lib.mps_set_tiles.argtypes = [P, ctypes.POINTER(mps_tile_choice), ctypes.c_int32]
+    lib.mps_set_tiles.restype = ctypes.c_int
     lib.mps_get_stats.argtypes = [P, ctypes.POINTER(mps_stats)]
     lib.mps_get_stats.restype = ctypes.c_int
     lib.mps_last_error.argtypes = []
@@ -244,6 +263,24 @@ def mps_sample_batch(h, chains, dtype: int, N: int, n_offset: int, seed: int) ->
     """Raw call over a list of mps_chain; returns the status code."""
     arr = (mps_chain * len(chains))(*chains)
     return load().mps_sample_batch(h, len(chains), arr, dtype, N, n_offset, ctypes.c_uint64(seed))
+
+
+def mps_autotune_tiles(h, chains, rows: int, seed: int = 0):
+    """Raw call over a list of mps_chain; returns (status, [mps_tile_choice])."""
+    arr = (mps_chain * len(chains))(*chains)
+    n = ctypes.c_int32(0)
+    rc = load().mps_autotune_tiles(h, len(chains), arr, rows, ctypes.c_uint64(seed), None, 0, ctypes.byref(n))
+    if rc:
+        return rc, []
+    out = (mps_tile_choice * max(1, n.value))()
+    rc = load().mps_autotune_tiles(h, len(chains), arr, rows, ctypes.c_uint64(seed), out, n.value, ctypes.byref(n))
+    return rc, list(out[:n.value]) if rc == 0 else []
+
+
+def mps_set_tiles(h, choices) -> int:
+    """Install a list of mps_tile_choice (an empty list clears); returns the status."""
+    arr = (mps_tile_choice * max(1, len(choices)))(*choices)
+    return load().mps_set_tiles(h, arr if choices else None, len(choices))
 
 
 def mps_get_stats(h) -> mps_stats:
@@ -414,6 +451,63 @@ class Sampler:
             with open(cache, "w") as f:
                 json.dump(table, f, indent=1, sort_keys=True)
         return dict(out, cached=False)
+
+    def autotune_tiles(self, chains, rows: int, seed: int = 0, stream=None, cache: str | None = None) -> list:
+        """Choose the contraction tile per site shape for `rows` samples per
+        launch (mps_autotune_tiles) and keep the choices in the handle.
+
+        chains: a list of site-tensor lists (one chain), a list of such lists,
+        or a PreparedBatch.  cache: optional JSON file of earlier choices,
+        keyed by precision, shape and rows; shapes found there are installed
+        with mps_set_tiles instead of being timed again.  Returns the choices
+        as dicts."""
+        import json
+        import torch
+        if isinstance(chains, PreparedBatch):
+            prep = chains
+        else:
+            lists = [chains] if chains and not isinstance(chains[0], (list, tuple)) else chains
+            prep = prepare_batch(lists)
+        shapes = set()
+        for c in prep.chains:
+            for t in c:
+                shapes.add((int(t.shape[0]), int(t.shape[1]), int(t.shape[2])))
+        key = lambda sh: "%d:%d:%d:%d:%d" % (self.opt.precision, sh[0], sh[1], sh[2], rows)
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+        if table and all(key(sh) in table for sh in shapes):
+            ch = [mps_tile_choice(*sh, int(table[key(sh)]["tile"]), rows, float(table[key(sh)]["ms_wide"]),
+                                  float(table[key(sh)]["ms_narrow"])) for sh in sorted(shapes)]
+            rc = mps_set_tiles(self.h, ch)
+            if rc:
+                raise MPSError(rc, mps_last_error())
+            return [dict(table[key(sh)], cached=True) for sh in sorted(shapes)]
+        opt = mps_options.from_buffer_copy(self.opt)
+        s = stream if stream is not None else torch.cuda.current_stream(torch.device("cuda", self.device))
+        opt.stream = s.cuda_stream
+        mps_set_options(self.h, opt)
+        rc, out = mps_autotune_tiles(self.h, prep.descs, rows, seed)
+        if rc:
+            raise MPSError(rc, mps_last_error())
+        res = []
+        for c in out:
+            d = {name: getattr(c, name) for name, _ in mps_tile_choice._fields_}
+            table[key((c.chi_l, c.d, c.chi_r))] = d
+            res.append(dict(d, cached=False))
+        if cache:
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+        return res
+
+    def set_tiles(self, choices) -> None:
+        """Install tile choices: dicts with chi_l, d, chi_r, tile, rows ([] clears)."""
+        ch = [mps_tile_choice(int(c["chi_l"]), int(c["d"]), int(c["chi_r"]), int(c["tile"]), int(c["rows"]),
+                              float(c.get("ms_wide", 0.0)), float(c.get("ms_narrow", 0.0))) for c in choices]
+        rc = mps_set_tiles(self.h, ch)
+        if rc:
+            raise MPSError(rc, mps_last_error())
 
     def sample_batch(self, chains, N: int, seed: int, n_offset: int = 0, want_logp: bool = True, stream=None,
                      raise_numeric: bool = False):

@@ -205,3 +205,25 @@ def test_noalloc_validates_on_host():
         assert "mps_sample_noalloc" in mps.mps_last_error()
     finally:
         mps.mps_destroy(h)
+
+
+def test_tile_choices_validated_on_host():
+    assert ctypes.sizeof(mps.mps_tile_choice) == 4 * 4 + 8 + 8 + 8
+    h = mps.mps_create(0)
+    try:
+        good = mps.mps_tile_choice(64, 4, 64, mps.MPS_TILE_NARROW, 8192, 0.0, 0.0)
+        assert mps.mps_set_tiles(h, [good]) == mps.MPS_OK
+        for bad in (mps.mps_tile_choice(64, 4, 64, 2, 8192, 0.0, 0.0),      # unknown tile
+                    mps.mps_tile_choice(0, 4, 64, 0, 8192, 0.0, 0.0),       # chi_l < 1
+                    mps.mps_tile_choice(64, 17, 64, 0, 8192, 0.0, 0.0),     # d > 16
+                    mps.mps_tile_choice(64, 4, 64, 0, 0, 0.0, 0.0)):        # rows < 1
+            assert mps.mps_set_tiles(h, [good, bad]) == mps.MPS_EINVAL
+        assert mps.mps_set_tiles(h, []) == mps.MPS_OK  # clears
+        c, keep = mps.make_chain([1, 1], [2, 4, 1], [4, 4], 0, 0, None)  # chi[0] != 1
+        rc, _ = mps.mps_autotune_tiles(h, [c], 1024)
+        assert rc == mps.MPS_EINVAL
+        c, keep = mps.make_chain([1, 1], [1, 4, 1], [4, 4], 0, 0, None)
+        rc, _ = mps.mps_autotune_tiles(h, [c], 0)  # rows < 1
+        assert rc == mps.MPS_EINVAL
+    finally:
+        mps.mps_destroy(h)
