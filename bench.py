@@ -110,6 +110,30 @@ def build_chain(args):
     return t128, t64, d, chi, name
 
 
+def tile_summary(choices, chains, seconds):
+    """Per-shape tile choices of mps_autotune_tiles, with the number of sites
+    of each shape (from the device tensors, one chain or a list of chains)
+    and the estimated contraction time saved over the wide tile."""
+    lists = chains if chains and isinstance(chains[0], (list, tuple)) else [chains]
+    count = {}
+    for c in lists:
+        for t in c:
+            sh = (int(t.shape[0]), int(t.shape[1]), int(t.shape[2]))
+            count[sh] = count.get(sh, 0) + 1
+    rows, wide, chosen = [], 0.0, 0.0
+    for c in choices:
+        n = count.get((c["chi_l"], c["d"], c["chi_r"]), 0)
+        wide += n * c["ms_wide"]
+        chosen += n * (c["ms_narrow"] if c["tile"] else c["ms_wide"])
+        rows.append([c["chi_l"], c["d"], c["chi_r"], n, "narrow" if c["tile"] else "wide",
+                     round(c["ms_wide"], 4), round(c["ms_narrow"], 4)])
+    rows.sort(key=lambda r: -r[3] * max(r[5], r[6]))
+    return {"shapes": len(choices), "narrow": sum(1 for c in choices if c["tile"]),
+            "est_contract_ms_wide": round(wide, 2), "est_contract_ms_chosen": round(chosen, 2),
+            "est_gain": round(wide / chosen, 4) if chosen > 0 else None, "tune_seconds": round(seconds, 1),
+            "by_shape (chi_l, d, chi_r, sites, tile, ms wide, ms narrow; heaviest first)": rows[:24]}
+
+
 def upload(t64, share=False):
     """One device buffer per site (pooled host tensors are copied once and
     cloned on the device), or, with share=True or device inputs, one buffer
@@ -266,10 +290,18 @@ def run_chain_bench(args):
         log(f"copy calibration: {args.copy_calibration} MiB device-to-device copy")
 
     tuned = {}
+    tiles = {}
 
     def run_form(form, steps, warmup):
         sampler = mps.Sampler(0, n_chunk=args.chunk, profile=not args.no_profile, precision=form,
                               graph=args.graph)
+        if args.tile_tune:
+            # contraction tile per distinct site shape at this chunk (outside
+            # the timed region; bit-identical whatever it picks)
+            t0 = time.perf_counter()
+            ch = sampler.autotune_tiles(dev, args.chunk)
+            tiles[form] = tile_summary(ch, dev, time.perf_counter() - t0)
+            log(f"{form} tiles: {tiles[form]['narrow']} of {tiles[form]['shapes']} shapes narrow")
         if args.autotune:
             # tile order (and chunk, capped at the step size) for this chain and
             # form; tuning time is outside the timed region
@@ -351,6 +383,8 @@ def run_chain_bench(args):
     }
     if tuned:
         rec["config"]["autotune"] = tuned
+    if tiles:
+        rec["config"]["tiles"] = tiles
     if beside:
         rec["beside"] = beside
         if "fp32" in beside:
@@ -478,12 +512,21 @@ def run_batch_bench(args):
     # chain descriptors (site pointers, bonds) are built once, like the upload
     prep = mps.prepare_batch(chains)
     res = {}
+    tiles = {}
     for form in [args.precision] + [f for f in args.beside.split(",") if f and f != args.precision]:
         sb = mps.Sampler(0, n_chunk=args.chunk, precision=form, fused_small=bool(args.fused_small))
+        choice = []
+        if args.tile_tune:
+            t0 = time.perf_counter()
+            choice = sb.autotune_tiles(prep, min(args.chunk, N))
+            tiles[form] = tile_summary(choice, chains, time.perf_counter() - t0)
+            log(f"{form} tiles: {tiles[form]['narrow']} of {tiles[form]['shapes']} shapes narrow")
         t_batch = timed(lambda: sb.sample_batch(prep, N, seed), args.steps)
         log(f"{form} batched: {t_batch * 1e3:.1f} ms")
         singles = [mps.Sampler(0, n_chunk=args.chunk, precision=form, mps_id=b, fused_small=bool(args.fused_small))
                    for b in range(len(chains))]
+        for s_ in singles:  # the same tile per shape as the batched call
+            s_.set_tiles(choice)
 
         def loop():
             for b, c in enumerate(chains):
@@ -511,6 +554,8 @@ def run_batch_bench(args):
         "speedup_batched_vs_per_chain": round(main["batched"] / main["per_chain_calls"], 3),
         "roofline": None, "cpu_baseline": None,
     }
+    if tiles:
+        rec["config"]["tiles"] = tiles
     print(json.dumps(rec), flush=True)
 
 
@@ -543,6 +588,7 @@ def main():
     ap.add_argument("--precision", default=None, choices=sorted(FORMS))
     ap.add_argument("--graph", type=int, default=0, help="replay one captured chunk graph per chunk")
     ap.add_argument("--autotune", type=int, default=1, help="pick the tile order with mps_autotune first")
+    ap.add_argument("--tile-tune", type=int, default=1, help="pick the tile shape per site shape first")
     ap.add_argument("--beside", default=None, help="comma-separated forms also timed ('' for none)")
     ap.add_argument("--beside-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")

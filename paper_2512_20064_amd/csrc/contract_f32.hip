@@ -214,11 +214,11 @@ __global__ __launch_bounds__(F32Tile<BM>::NTHR, 2) void contract_f32_kernel(cons
     }
   }
 
-  // Epilogue 2: partial weights per 32 complex columns (one per wave column
-  // of the tile).  Columns past chi_r were zero-filled, so they add nothing.
-  // Reduction order is fixed (the two blocks of a lane, then the lanes by xor
-  // butterfly), so the result depends neither on scheduling nor on the
-  // variant.
+  // Epilogue 2: partial weight of this (row, branch, 64-column tile).
+  // Columns past chi_r were zero-filled, so they add nothing.  Reduction
+  // order is fixed (the two blocks of a lane, the lanes by xor butterfly,
+  // then the two wave columns of the tile), so the result depends neither on
+  // scheduling nor on the variant (both have the same two wave columns).
   float* red = lds;  // the stages are free: the K loop ended on a barrier
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb) {
@@ -229,18 +229,13 @@ __global__ __launch_bounds__(F32Tile<BM>::NTHR, 2) void contract_f32_kernel(cons
       for (int cb = 0; cb < 2; ++cb) s += tot[rb][cb][v] * tot[rb][cb][v];
 #pragma unroll
       for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off, 32);
-      if (j == 0) red[(wr + rb * 32 + (v >> 2) * 8 + half * 4 + (v & 3)) * 2 + (wave & 1)] = s;
+      if (j == 0) red[(wave & 1) * BM + wr + rb * 32 + (v >> 2) * 8 + half * 4 + (v & 3)] = s;
     }
   }
   __syncthreads();
   if (tid < BM) {
     const int gr = m0 + tid;
-    const int TP = fp32_parts(a.chi_r);
-    if (gr < rows) {
-      float* dst = a.qpart + (size_t)gr * (a.d * TP) + branch * TP + 2 * ct;
-      dst[0] = red[2 * tid];
-      dst[1] = red[2 * tid + 1];
-    }
+    if (gr < rows) a.qpart[(size_t)gr * (a.d * T) + branch * T + ct] = red[tid] + red[BM + tid];
   }
 }
 

@@ -163,28 +163,25 @@ __device__ inline void load_slot(int idx, int NL, int& q, int& rg, int& ldst) {
   }
 }
 
-// Partial branch weights of the tile (fixed granularity: 32 complex columns
-// = cb blocks {0,1} and {2,3} of a wave), summed per lane over the two
-// blocks, across the 32 lanes of a half by an xor butterfly, staged in LDS
-// and stored as one run of partials per row.  The order of every addition is
-// the same in every variant.
+// Partial branch weights of the tile, one per wave column (fixed
+// granularity: 64 complex columns = the 4 column blocks of a wave), summed
+// per lane over the blocks in order, across the 32 lanes of a half by an xor
+// butterfly, staged in LDS and stored as one run of partials per row.  The
+// order of every addition is the same in both variants.
 template <int NWC>
 __device__ inline void store_partials(const floatx16 (&acc)[2][4], float* red, int wave, int wr, int half, int j,
                                       int tid, int m0, int rows, float* qpart, size_t qrow, int q0) {
-  constexpr int NG = 2 * NWC;  // 32-column groups per tile
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb) {
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
+      float s = 0.f;
 #pragma unroll
-      for (int g = 0; g < 2; ++g) {
-        float s = acc[rb][2 * g][v] * acc[rb][2 * g][v];
-        s += acc[rb][2 * g + 1][v] * acc[rb][2 * g + 1][v];
+      for (int cb = 0; cb < 4; ++cb) s += acc[rb][cb][v] * acc[rb][cb][v];
 #pragma unroll
-        for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off, 32);
-        const int r = wr + rb * 32 + (v >> 2) * 8 + half * 4 + (v & 3);
-        if (j == 0) red[r * NG + (NWC == 2 ? (wave & 1) * 2 : 0) + g] = s;
-      }
+      for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off, 32);
+      const int r = wr + rb * 32 + (v >> 2) * 8 + half * 4 + (v & 3);
+      if (j == 0) red[r * NWC + wave % NWC] = s;
     }
   }
   __syncthreads();
@@ -193,7 +190,7 @@ __device__ inline void store_partials(const floatx16 (&acc)[2][4], float* red, i
     if (gr < rows) {
       float* dst = qpart + (size_t)gr * qrow + q0;
 #pragma unroll
-      for (int g = 0; g < NG; ++g) dst[g] = red[tid * NG + g];
+      for (int g = 0; g < NWC; ++g) dst[g] = red[tid * NWC + g];
     }
   }
 }
@@ -371,7 +368,7 @@ __global__ __launch_bounds__(LpTile<NWC>::NTHR, 1) void contract_lp_kernel(const
       }
     }
   }
-  // Epilogue 2: partial weights per 32 complex columns; padded columns are
+  // Epilogue 2: partial weights per 64 complex columns; padded columns are
   // exact zeros.
   const int TP = a.CP / kPartCols;  // partials per branch
   store_partials<NWC>(acc, reinterpret_cast<float*>(lds), wave, wr, half, j, tid, m0, rows, a.qpart,

@@ -610,6 +610,14 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
     }
     init_off[s] = tab.put(init);
     for (int k = 0; k < Mmax; ++k) {
+      // One tile for the whole step: the choice of the shapes that carry most
+      // of the step's flops (a step split into two launches of fewer
+      // workgroups each fills the GPU worse than either tile alone).
+      double vote[2] = {0.0, 0.0};
+      for (const Chain& c : chains)
+        if (k < c.M)
+          vote[tile_for(h, c.chi[k], c.d[k], c.chi[k + 1], nc)] += (double)c.chi[k] * c.d[k] * c.chi[k + 1];
+      const int tile = vote[1] > vote[0] ? (int)mps::kTileNarrow : (int)mps::kTileWide;
       std::vector<mps::ContractProb> cf[2];
       std::vector<mps::ContractLpProb> cl[2];
       std::vector<mps::PackProb> pk;
@@ -620,7 +628,6 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
         const Chain& c = chains[b];
         if (k >= c.M) continue;
         const int K = c.chi[k], dk = c.d[k], chr = c.chi[k + 1];
-        const int tile = tile_for(h, K, dk, chr, nc);
         int T;
         if (lowp) {
           const int CP = mps::lp_pad_cols(chr, tile), Kp = mps::lp_pad_k(K);

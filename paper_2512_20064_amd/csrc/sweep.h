@@ -28,10 +28,10 @@ __host__ __device__ inline int col_tiles(int chi_r) { return (chi_r + kBNC - 1) 
 //           (2 waves);
 //   16-bit  wide 256 x 128 (8 waves), narrow 256 x 64 (4 waves).
 enum TileVariant { kTileWide = 0, kTileNarrow = 1 };
-// Partial branch weights: one per row, branch and 32 complex columns, in
+// Partial branch weights: one per row, branch and 64 complex columns, in
 // every kernel and variant (the measurement sums them in FP64 in order).
-constexpr int kPartCols = 32;
-__host__ __device__ inline int fp32_parts(int chi_r) { return 2 * col_tiles(chi_r); }
+constexpr int kPartCols = 64;
+__host__ __device__ inline int fp32_parts(int chi_r) { return col_tiles(chi_r); }
 
 // ---- 16-bit contraction tile: kLpBM samples x kLpBNC (wide) or kLpBNC/2
 // (narrow) complex columns of one branch; K in stages of kLpBK real values.
