@@ -96,16 +96,17 @@ def test_chi10000_streamed_window_prefix_parity(form):
     print("prefix call", rep, flush=True)
 
 
-def test_uneven_chain_prefix_parity():
+@pytest.mark.parametrize("form", ["bf16x3", "fp16f8"])
+def test_uneven_chain_prefix_parity(form):
     from paper_2512_20064_amd import mps
     from tests.parity_util import compare
-    print("[gpu-case] uneven M=2048 chi<=4096, 8192-sample chunk, bf16x3", flush=True)
+    print(f"[gpu-case] uneven M=2048 chi<=4096, 8192-sample chunk, {form}", flush=True)
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([4, 0, 0xD])))
     dl = [int(x) for x in rng.integers(2, 7, size=2048)]
     sites, bonds = synth.structured_chain(4, dl, 4096, pool=2, device="cuda")
     N, seed = 8192, 1003
     P = 10
-    s = mps.Sampler(0, n_chunk=8192, precision="bf16x3")
+    s = mps.Sampler(0, n_chunk=8192, precision=form)
     r = s.sample(sites, N, seed, emit_n=N, emit_dmax=6)
     torch.cuda.synchronize()
     assert r["status"] == 0

@@ -333,3 +333,21 @@ def test_small_bond_kernel_runs_and_agrees_with_per_site_launches(mpsmod):
     a.close()
     b.close()
     c.close()
+
+
+@pytest.mark.parametrize("form", ["fp16f8", "bf16x3"])
+def test_power_of_two_site_scaling_is_exact(mpsmod, form):
+    """Every site multiplied by 2^-20 or 2^12 (a non-canonical input that the
+    sampler normalises by S): fp16f8 absorbs the factor into its per-column
+    power-of-two scales and bf16 keeps FP32's exponent range, so W, the
+    branch weights and S scale by exact powers of two and the outcomes, logp
+    and conditional probabilities are bit-identical to the unscaled run."""
+    _say(f"power-of-two site scaling {form}")
+    t = _chain(13, 16, 4, 64)
+    ref = _run(mpsmod, t, 1200, seed=31, emit_n=1200, precision=form)
+    for e in (-20, 12):
+        ts = [np.ascontiguousarray(x * np.float32(2.0 ** e)) for x in t]
+        g = _run(mpsmod, ts, 1200, seed=31, emit_n=1200, precision=form)
+        assert np.array_equal(g["outcomes"], ref["outcomes"]), e
+        assert np.array_equal(g["logp"].view(np.uint64), ref["logp"].view(np.uint64)), e
+        assert np.array_equal(g["probs"], ref["probs"], equal_nan=True), e
