@@ -57,8 +57,12 @@ FORMS = {
                "dtype": "f16x3"},
     # one fp16 product plus two FP8 products at twice the fp16 rate: two
     # fp16-product equivalents of MFMA time per complex product
-    "fp16f8": {"peak": 2516.6, "mfma_per_alg": 2, "kernel": "contract_f16f8_kernel", "src": "contract_lp.hip",
+    "fp16f8": {"peak": 2516.6, "mfma_per_alg": 2, "kernel": "contract_f16f8_wide", "src": "contract_lp.hip",
                "dtype": "f16+f8"},
+    # the same with the two correction products in FP6 at four times the
+    # fp16 rate: 1.5 fp16-product equivalents
+    "fp16f6": {"peak": 2516.6, "mfma_per_alg": 1.5, "kernel": "contract_f16f6_wide", "src": "contract_lp.hip",
+               "dtype": "f16+f6"},
 }
 
 

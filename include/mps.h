@@ -67,7 +67,7 @@ enum {
                         products as MPS_BF16X3 on v_mfma_f32_32x32x16_f16; 11-bit
                         parts (22 bits together) but a narrower exponent range:
                         lo parts below 2^-24 flush to zero                        */
-  MPS_FP16F8 = 4     /* split precision with FP8 corrections: W = Lh*Ah in fp16 on
+  MPS_FP16F8 = 4,    /* split precision with FP8 corrections: W = Lh*Ah in fp16 on
                         v_mfma_f32_32x32x16_f16 plus the two correction products
                         Lh*Al + Ll*Ah in OCP FP8 E4M3 on the block-scaled
                         v_mfma_scale_f32_32x32x64_f8f6f4 (one FP8 instruction per
@@ -80,6 +80,14 @@ enum {
                         corrections need only a few significant bits each: two
                         fp16-product equivalents of MFMA time per complex product
                         instead of three.                                         */
+  MPS_FP16F6 = 5     /* MPS_FP16F8 with the two correction products in OCP FP6
+                        E2M3 (3 mantissa bits, magnitudes 2^-3 .. 7.5) on the same
+                        instruction at twice the FP8 rate: 1.5 fp16-product
+                        equivalents per complex product.  E2M3's range is narrow,
+                        so every 32 correction values of a row (column) and 16-K
+                        slice carry their own power-of-two scale.  No displaced
+                        measurement: mps_options.displace must be NULL
+                        (MPS_EINVAL otherwise).                                   */
 };
 
 /* Storage of the site tensors (Section 3.3.2: tensors stored and moved in
@@ -121,7 +129,8 @@ enum {
 typedef struct mps_ctx* mps_handle;
 
 typedef struct {
-  int32_t precision;        /* MPS_FP32, MPS_BF16X3, MPS_FP16, MPS_FP16X3, MPS_FP16F8 */
+  int32_t precision;        /* MPS_FP32, MPS_BF16X3, MPS_FP16, MPS_FP16X3, MPS_FP16F8,
+                               MPS_FP16F6                                           */
   int32_t profile;          /* 1: time every kernel launch with HIP events        */
   int64_t n_chunk;          /* samples per pass over the chain; 0 = planner picks */
   int64_t max_device_bytes; /* cap on scratch bytes; 0 = no cap                  */
@@ -324,10 +333,10 @@ int mps_autotune(mps_handle h, const void* const* tensors, int32_t dtype,
 
 /* Contraction tile shapes.  Every precision form has two; both give the same
  * bits (each output is accumulated over K in the same order, and the branch
- * weights are summed from partials of 32 complex columns whatever the tile):
- *   MPS_TILE_WIDE    FP32 128 samples x 64 complex columns; 16-bit and
- *                    MPS_FP16F8 256 x 128 (the default);
- *   MPS_TILE_NARROW  FP32 64 x 64; 16-bit and MPS_FP16F8 256 x 64 (half the
+ * weights are summed from partials of 64 complex columns whatever the tile):
+ *   MPS_TILE_WIDE    FP32 128 samples x 64 complex columns; 16-bit,
+ *                    MPS_FP16F8 and MPS_FP16F6 256 x 128 (the default);
+ *   MPS_TILE_NARROW  FP32 64 x 64; the others 256 x 64 (half the
  *                    column padding for thin bonds, twice the workgroups).  */
 #define MPS_TILE_WIDE 0
 #define MPS_TILE_NARROW 1

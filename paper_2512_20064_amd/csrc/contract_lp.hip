@@ -18,6 +18,9 @@
 //           so per 32 real K a 32x32 block costs two fp16 MFMAs (32 cycles
 //           each) and one FP8 MFMA (64 cycles), against six 16-bit MFMAs
 //           for bf16x3.
+//   fp16f6  fp16f8 with the corrections in FP6 E2M3, one power-of-two scale
+//           per 32-value lane record (sweep.h, kFp16F6): the FP6 instruction
+//           runs at twice the FP8 rate, 96 cycles per 32 real K.
 //
 // Complex arithmetic uses the real embedding of the site tensor: real column
 // (c, p) of branch i multiplies the interleaved left vector (re, im) by
@@ -31,6 +34,7 @@
 // multiply-add; its cost is that the site-tensor operand is twice as large
 // as the complex data, which only matters for L2/LDS traffic.
 
+#include "e2m3.h"
 #include "sweep.h"
 #include "tiling.h"
 
@@ -335,7 +339,24 @@ __global__ __launch_bounds__(LpTile<NWC>::NTHR, 1) void contract_lp_kernel(const
   Ops o0, o1;
   open_stage(0);
   lds_read(0, o0);
-  for (int kt = 0; kt < nkt; kt += 2) {
+  // Steady state: `issued` = s + NST - 1 at every open, so the wait keeps
+  // NST - 2 stages in flight and one stage is issued; as straight-line code
+  // (no branch in the step) the compiler keeps the MFMAs ahead of the
+  // barrier.  The last stages take the general step below.
+  int kt = 0;
+  for (; kt + NST + 1 < nkt; kt += 2) {
+    __builtin_amdgcn_s_waitcnt(vmcnt_lgkm0_imm((NST - 2) * IPW));
+    asm volatile("s_barrier" ::: "memory");
+    issue(issued++);
+    lds_read(kt + 1, o1);
+    mma(o0);
+    __builtin_amdgcn_s_waitcnt(vmcnt_lgkm0_imm((NST - 2) * IPW));
+    asm volatile("s_barrier" ::: "memory");
+    issue(issued++);
+    lds_read(kt + 2, o0);
+    mma(o1);
+  }
+  for (; kt < nkt; kt += 2) {
     open_stage(kt + 1);  // kt + 1 < nkt: nkt is even
     lds_read(kt + 1, o1);
     mma(o0);
@@ -379,6 +400,7 @@ __global__ __launch_bounds__(LpTile<NWC>::NTHR, 1) void contract_lp_kernel(const
 
 typedef int intx4 __attribute__((ext_vector_type(4)));
 typedef int intx8 __attribute__((ext_vector_type(8)));
+typedef int intx2 __attribute__((ext_vector_type(2)));
 
 // E8M0 scale codes of the FP8 products: 2^-19 on the left-vector operand
 // (the common factor of both corrections), 2^0 on the site tensor's.
@@ -441,7 +463,11 @@ __global__ __launch_bounds__(256) void colmax_kernel(const PackProb* probs, cons
 // Packing of the fp16f8 operands: the same tiles as pack_kernel; each real
 // value v (column already divided by its scale) gives h = fp16(v) into the
 // 16-bit plane and the codes e4m3(h), e4m3((v - h) * 2^11) into the pair
-// plane (low part first: [B8l | B8h]).
+// plane (low part first: [B8l | B8h]).  F6 (fp16f6): the same two values per
+// K as E2M3 codes of one 32-value record per packed row and 16-K slice
+// (low parts codes 0..15, high parts 16..31), scaled by the record's
+// power of two.
+template <bool F6>
 __global__ __launch_bounds__(256) void pack_f16f8_kernel(const PackProb* probs, const int* blk_start, int nprob) {
   __shared__ float2 tile[PK_L][PK_P];
   const int p = find_problem(blk_start, nprob, blockIdx.x);
@@ -506,10 +532,38 @@ __global__ __launch_bounds__(256) void pack_f16f8_kernel(const PackProb* probs, 
     const size_t orow = ((size_t)br * a.CP + c0 + c) * 2 + p;
     const int k = 2 * l0 + ch * 8;
     *reinterpret_cast<f16x8*>(Bh + kblk_off(orow, k, a.Kp)) = h;
-    unsigned char* d8 = B8 + pair_off(orow, k, a.Kp);
-    *reinterpret_cast<uint2*>(d8) = make_uint2(e4m3x4(lo[0], lo[1], lo[2], lo[3]), e4m3x4(lo[4], lo[5], lo[6], lo[7]));
-    *reinterpret_cast<uint2*>(d8 + 16) =
-        make_uint2(e4m3x4(hf[0], hf[1], hf[2], hf[3]), e4m3x4(hf[4], hf[5], hf[6], hf[7]));
+    if constexpr (!F6) {
+      unsigned char* d8 = B8 + pair_off(orow, k, a.Kp);
+      *reinterpret_cast<uint2*>(d8) = make_uint2(e4m3x4(lo[0], lo[1], lo[2], lo[3]), e4m3x4(lo[4], lo[5], lo[6], lo[7]));
+      *reinterpret_cast<uint2*>(d8 + 16) =
+          make_uint2(e4m3x4(hf[0], hf[1], hf[2], hf[3]), e4m3x4(hf[4], hf[5], hf[6], hf[7]));
+    } else {
+      // The record of this packed row's 16-K slice: threads ch and ch^1
+      // (adjacent lanes) hold its two halves; the scale is their common max.
+      float m = 0.f;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) m = fmaxf(m, fmaxf(fabsf(hf[e]), fabsf(lo[e])));
+      m = fmaxf(m, __shfl_xor(m, 1));
+      // (at least 2^-108, so that the stored scale code 127 + ke - 19 >= 0;
+      // a record that small flushes to zero)
+      const int ke = max(e2m3_scale_exp(m), -108);
+      const float inv2 = ldexpf(1.f, -ke);
+      unsigned cl[8], chh[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        cl[e] = e2m3_code(lo[e] * inv2);
+        chh[e] = e2m3_code(hf[e] * inv2);
+      }
+      // site record: codes 0..15 the low part, 16..31 the high part; this
+      // thread's 8 K values are codes (k & 8) .. +7 of each half
+      unsigned char* rec = B8 + pair_off(orow, k & ~15, a.Kp);
+      const int q = (k & 8) ? 1 : 0;
+      e2m3_store8(rec + 6 * q, cl);
+      e2m3_store8(rec + 12 + 6 * q, chh);
+      // byte 24: the scale (the corrections' common 2^-19 rides on the site's
+      // scale); bytes 25..31 zero
+      *reinterpret_cast<uint32_t*>(rec + 24 + 4 * q) = q == 0 ? (uint32_t)(127 + ke - 19) : 0u;
+    }
   }
 }
 
@@ -526,7 +580,7 @@ __global__ __launch_bounds__(256) void pack_f16f8_kernel(const PackProb* probs, 
 // (LDS-read wait before the barrier).
 // (The body is a device function template with one plain kernel per
 // variant below.)
-template <int NWC>
+template <int NWC, bool F6>
 __device__ inline void contract_f16f8_body(const ContractLpProb* probs, const int* tn_start, int nprob, int tn_total,
                                            int tiles_m, int per_xcd, int group_m, const ChunkArgs* chp) {
   typedef LpTile<NWC> Tile;
@@ -623,16 +677,31 @@ __device__ inline void contract_f16f8_body(const ContractLpProb* probs, const in
     for (int cb = 0; cb < 4; ++cb) o.b[cb] = *reinterpret_cast<const f16x8*>(st + b_h + cb * 1024);
   };
   auto cat = [](intx4 x, intx4 y) -> intx8 { return __builtin_shufflevector(x, y, 0, 1, 2, 3, 4, 5, 6, 7); };
+  // FP6 records: dwords 0..5 codes, dword 6 scale, dword 7 unused (not read)
+  auto rec6 = [](const char* q0, const char* q1) -> intx8 {
+    const intx4 x = *reinterpret_cast<const intx4*>(q0);
+    const intx2 y = *reinterpret_cast<const intx2*>(q1);
+    const int sc = *reinterpret_cast<const int*>(q1 + 8);
+    return intx8{x[0], x[1], x[2], x[3], y[0], y[1], sc, sc};
+  };
   auto read8 = [&](int m, Ops8& o) {
     const char* st = lds + ((2 * m + half) % NST) * STAGE;  // lane half h: slice 2m + h
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-      o.a[rb] = cat(*reinterpret_cast<const intx4*>(st + a8_0 + rb * 1024),
-                    *reinterpret_cast<const intx4*>(st + a8_1 + rb * 1024));
+    for (int rb = 0; rb < 2; ++rb) {
+      if constexpr (F6)
+        o.a[rb] = rec6(st + a8_0 + rb * 1024, st + a8_1 + rb * 1024);
+      else
+        o.a[rb] = cat(*reinterpret_cast<const intx4*>(st + a8_0 + rb * 1024),
+                      *reinterpret_cast<const intx4*>(st + a8_1 + rb * 1024));
+    }
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
-      o.b[cb] = cat(*reinterpret_cast<const intx4*>(st + b8_0 + cb * 1024),
-                    *reinterpret_cast<const intx4*>(st + b8_1 + cb * 1024));
+    for (int cb = 0; cb < 4; ++cb) {
+      if constexpr (F6)
+        o.b[cb] = rec6(st + b8_0 + cb * 1024, st + b8_1 + cb * 1024);
+      else
+        o.b[cb] = cat(*reinterpret_cast<const intx4*>(st + b8_0 + cb * 1024),
+                      *reinterpret_cast<const intx4*>(st + b8_1 + cb * 1024));
+    }
   };
   auto mma16 = [&](const Ops16& o) {
 #pragma unroll
@@ -640,13 +709,20 @@ __device__ inline void contract_f16f8_body(const ContractLpProb* probs, const in
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(o.a[rb], o.b[cb], acc[rb][cb], 0, 0, 0);
   };
+  // FP6: formats 2 (E2M3) on both sides; the first six dwords of a lane's
+  // record are its 32 codes, the low byte of the seventh its scale.
   auto mma8 = [&](const Ops8& o) {
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb)
-        acc[rb][cb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(o.a[rb], o.b[cb], acc[rb][cb], 0, 0, 0, kScale8L,
-                                                                      0, kScale8B);
+      for (int cb = 0; cb < 4; ++cb) {
+        if constexpr (F6)
+          acc[rb][cb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(o.a[rb], o.b[cb], acc[rb][cb], 2, 2, 0,
+                                                                        o.a[rb][6], 0, o.b[cb][6]);
+        else
+          acc[rb][cb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(o.a[rb], o.b[cb], acc[rb][cb], 0, 0, 0,
+                                                                        kScale8L, 0, kScale8B);
+      }
   };
 
   const int nkt = a.Kp / BK;  // a multiple of 4
@@ -674,7 +750,29 @@ __device__ inline void contract_f16f8_body(const ContractLpProb* probs, const in
   read8(0, f);
   // (sched_barrier: the compiler keeps this order instead of hoisting the
   // next reads above the MFMAs, which would need a third register set)
-  for (int m = 0; m < npair; ++m) {
+  // Steady state, pairs 0 .. npair-4: every step opens the next pair and
+  // issues two slices.  Straight-line code (no branch inside the step), so
+  // that the MFMAs stay ahead of the barrier and the LDS-read waits before
+  // mma16(h) cover the reads of h only; the last three pairs take the
+  // general step below.
+  int m = 0;
+  for (; m + 3 < npair; ++m) {
+    mma16(e);
+    __builtin_amdgcn_sched_barrier(0);
+    read16(2 * m + 1, h);
+    mma8(f);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(vmcnt_lgkm0_imm(IPW));
+    asm volatile("s_barrier" ::: "memory");
+    issue(issued++);
+    issue(issued++);
+    __builtin_amdgcn_sched_barrier(0);
+    read16(2 * m + 2, e);
+    mma16(h);
+    __builtin_amdgcn_sched_barrier(0);
+    read8(m + 1, f);
+  }
+  for (; m < npair; ++m) {
     mma16(e);
     __builtin_amdgcn_sched_barrier(0);
     read16(2 * m + 1, h);
@@ -728,13 +826,25 @@ __global__ __launch_bounds__(LpTile<2>::NTHR, 1) void contract_f16f8_wide(const 
                                                                           const int* tn_start, int nprob, int tn_total,
                                                                           int tiles_m, int per_xcd, int group_m,
                                                                           const ChunkArgs* chp) {
-  contract_f16f8_body<2>(probs, tn_start, nprob, tn_total, tiles_m, per_xcd, group_m, chp);
+  contract_f16f8_body<2, false>(probs, tn_start, nprob, tn_total, tiles_m, per_xcd, group_m, chp);
 }
 __global__ __launch_bounds__(LpTile<1>::NTHR, 1) void contract_f16f8_narrow(const ContractLpProb* probs,
                                                                             const int* tn_start, int nprob,
                                                                             int tn_total, int tiles_m, int per_xcd,
                                                                             int group_m, const ChunkArgs* chp) {
-  contract_f16f8_body<1>(probs, tn_start, nprob, tn_total, tiles_m, per_xcd, group_m, chp);
+  contract_f16f8_body<1, false>(probs, tn_start, nprob, tn_total, tiles_m, per_xcd, group_m, chp);
+}
+__global__ __launch_bounds__(LpTile<2>::NTHR, 1) void contract_f16f6_wide(const ContractLpProb* probs,
+                                                                          const int* tn_start, int nprob, int tn_total,
+                                                                          int tiles_m, int per_xcd, int group_m,
+                                                                          const ChunkArgs* chp) {
+  contract_f16f8_body<2, true>(probs, tn_start, nprob, tn_total, tiles_m, per_xcd, group_m, chp);
+}
+__global__ __launch_bounds__(LpTile<1>::NTHR, 1) void contract_f16f6_narrow(const ContractLpProb* probs,
+                                                                            const int* tn_start, int nprob,
+                                                                            int tn_total, int tiles_m, int per_xcd,
+                                                                            int group_m, const ChunkArgs* chp) {
+  contract_f16f8_body<1, true>(probs, tn_start, nprob, tn_total, tiles_m, per_xcd, group_m, chp);
 }
 
 template <typename T, int NPROD>
@@ -771,6 +881,12 @@ hipError_t launch_f16f8(int tile, const ContractLpProb* probs, const int* tn_sta
   MPS_CONTRACT_LAUNCH(contract_f16f8_wide, LpTile<2>::NTHR);
 }
 
+hipError_t launch_f16f6(int tile, const ContractLpProb* probs, const int* tn_start, int nprob, int tn_total,
+                        const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s) {
+  if (tile == kTileNarrow) MPS_CONTRACT_LAUNCH(contract_f16f6_narrow, LpTile<1>::NTHR);
+  MPS_CONTRACT_LAUNCH(contract_f16f6_wide, LpTile<2>::NTHR);
+}
+
 }  // namespace
 
 hipError_t launch_colscale(const PackProb* probs, const int* cm_start, int nprob, int cm_total, hipStream_t s) {
@@ -781,9 +897,14 @@ hipError_t launch_colscale(const PackProb* probs, const int* cm_start, int nprob
 
 hipError_t launch_pack_lp(int form, const PackProb* probs, const int* blk_start, int nprob, int blk_total,
                           hipStream_t s) {
+  if (form == kFp16F6) {
+    if (nprob <= 0 || blk_total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pack_f16f8_kernel<true>, dim3(blk_total), dim3(256), 0, s, probs, blk_start, nprob);
+    return hipGetLastError();
+  }
   if (form == kFp16F8) {
     if (nprob <= 0 || blk_total <= 0) return hipSuccess;
-    hipLaunchKernelGGL(pack_f16f8_kernel, dim3(blk_total), dim3(256), 0, s, probs, blk_start, nprob);
+    hipLaunchKernelGGL(pack_f16f8_kernel<false>, dim3(blk_total), dim3(256), 0, s, probs, blk_start, nprob);
     return hipGetLastError();
   }
   if (form == kBf16x3) return launch_pack_t<bf16_t, 3>(probs, blk_start, nprob, blk_total, s);
@@ -794,6 +915,7 @@ hipError_t launch_pack_lp(int form, const PackProb* probs, const int* blk_start,
 hipError_t launch_contract_lp(int form, int tile, const ContractLpProb* probs, const int* tn_start, int nprob,
                               int tn_total, const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s) {
   if (form == kFp16F8) return launch_f16f8(tile, probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s);
+  if (form == kFp16F6) return launch_f16f6(tile, probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s);
   if (form == kBf16x3)
     return launch_contract_t<bf16_t, 3>(tile, probs, tn_start, nprob, tn_total, ch, grid_rows, group_m, s);
   if (form == kFp16x3)

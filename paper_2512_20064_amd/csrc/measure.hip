@@ -31,6 +31,7 @@
 // (measure_kernel) one wave measures one row: it builds that row's D in its
 // LDS and forms the weights from W' directly.
 
+#include "e2m3.h"
 #include "philox.h"
 #include "sweep.h"
 
@@ -44,7 +45,7 @@ typedef _Float16 f16_t;
 
 constexpr int DMAX = 16;
 
-enum Out { kOutF32 = 0, kOutBf16x2 = 1, kOutF16 = 2, kOutF16x2 = 3, kOutF16F8 = 4 };
+enum Out { kOutF32 = 0, kOutBf16x2 = 1, kOutF16 = 2, kOutF16x2 = 3, kOutF16F8 = 4, kOutF16F6 = 5 };
 
 // Left-vector writers for the three operand formats.
 template <int OUT>
@@ -224,6 +225,58 @@ struct LWriter<kOutF16F8> {
       const size_t o = pair_off(row, k, ld);
       *reinterpret_cast<uint2*>(p8 + o) = make_uint2(0u, 0u);
       *reinterpret_cast<uint2*>(p8 + o + 16) = make_uint2(0u, 0u);
+    }
+  }
+};
+
+// fp16f6 writer: the fp16 plane as fp16f8, and per 16-K slice one E2M3
+// record of the 32 values Lh * 2^8 (codes 0..15) and (x - Lh) * 2^19 (codes
+// 16..31) divided by the record's power of two 2^k (E8M0 code 127 + k in
+// byte 24).  A record needs the whole slice, so this writer takes pieces of
+// 8 complex (put8) and the measurement never hands it single values.
+template <>
+struct LWriter<kOutF16F6> {
+  uint32_t* hi;
+  unsigned char* p6;
+  size_t row;
+  int ld;
+  __device__ LWriter(const MeasureProb& a, int r)
+      : hi((uint32_t*)a.Lh), p6((unsigned char*)a.Ll), row((size_t)r), ld(a.ld_out) {}
+  // complex r8 .. r8+7: the 16 K values 2*r8 .. 2*r8+15 of one slice
+  __device__ void put8(int r8, const float2 (&v)[8]) {
+    float hv[16], lv[16];
+    uint32_t h[8];
+    float m = 0.f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const f16_t xh = (f16_t)v[j].x, yh = (f16_t)v[j].y;
+      h[j] = (uint32_t)__builtin_bit_cast(uint16_t, xh) | ((uint32_t)__builtin_bit_cast(uint16_t, yh) << 16);
+      const float xf = (float)xh, yf = (float)yh;
+      hv[2 * j] = xf * 256.f;
+      hv[2 * j + 1] = yf * 256.f;
+      lv[2 * j] = (v[j].x - xf) * 524288.f;
+      lv[2 * j + 1] = (v[j].y - yf) * 524288.f;
+      m = fmaxf(m, fmaxf(fmaxf(fabsf(hv[2 * j]), fabsf(hv[2 * j + 1])), fmaxf(fabsf(lv[2 * j]), fabsf(lv[2 * j + 1]))));
+    }
+    *reinterpret_cast<uint4*>(hi + (kblk_off(row, 2 * r8, ld) >> 1)) = make_uint4(h[0], h[1], h[2], h[3]);
+    *reinterpret_cast<uint4*>(hi + (kblk_off(row, 2 * r8 + 8, ld) >> 1)) = make_uint4(h[4], h[5], h[6], h[7]);
+    const int k = e2m3_scale_exp(m);
+    const float inv = ldexpf(1.f, -k);
+    unsigned c[32];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      c[e] = e2m3_code(hv[e] * inv);
+      c[16 + e] = e2m3_code(lv[e] * inv);
+    }
+    e2m3_store_record(p6 + pair_off(row, 2 * r8, ld), c, (unsigned)(127 + k));
+  }
+  __device__ void pad_from(int k0, int sl, int W) {
+    for (int k = k0 + 16 * sl; k < ld; k += 16 * W) {
+      *reinterpret_cast<uint4*>(hi + (kblk_off(row, k, ld) >> 1)) = make_uint4(0u, 0u, 0u, 0u);
+      *reinterpret_cast<uint4*>(hi + (kblk_off(row, k + 8, ld) >> 1)) = make_uint4(0u, 0u, 0u, 0u);
+      uint4* d = reinterpret_cast<uint4*>(p6 + pair_off(row, k, ld));
+      d[0] = make_uint4(0u, 0u, 0u, 0u);
+      d[1] = make_uint4(0u, 0u, 127u, 0u);
     }
   }
 };
@@ -515,10 +568,14 @@ __global__ __launch_bounds__(256) void measure_rows_kernel(const MeasureProb* pr
   // least four rows at a time (chi_r = 1024, bf16 hi+lo: 187 us per 65536-row
   // launch against 273 us with the whole wave on one row; 32 and 8 lanes: 214
   // and 202 us)
-  const int W = meas_lanes(a.chi_r) < 16 ? meas_lanes(a.chi_r) : 16;
+  // pieces of PC complex: 4 (half a 16-K slice), or a whole slice for the
+  // fp16f6 records
+  constexpr int PC = OUT == kOutF16F6 ? 8 : 4;
+  const int ml = meas_lanes(PC == 8 ? (a.chi_r + 1) >> 1 : a.chi_r);  // pieces rounded up to a power of two
+  const int W = ml < 16 ? ml : 16;
   const int G = 64 / W;               // rows per wave step
   const int g = lane / W, sl = lane & (W - 1);
-  const int nq = (a.chi_r + 3) >> 2;  // pieces of 4 complex per row
+  const int nq = (a.chi_r + PC - 1) / PC;  // pieces per row
   const int iters = (nq + W - 1) / W;
   const int nsteps = (kRowsPerBlock + 4 * G - 1) / (4 * G);
   const bool even = (a.chi_r & 1) == 0;  // a piece is then 16-byte aligned
@@ -526,39 +583,42 @@ __global__ __launch_bounds__(256) void measure_rows_kernel(const MeasureProb* pr
   for (int t = 0; t < nsteps * iters; ++t) {
     const int k = t / iters, it = t - k * iters;
     const int rloc = (k * 4 + wv) * G + g;
-    const int q4 = sl + it * W;
-    if (rloc >= kRowsPerBlock || q4 >= nq) continue;
+    const int qp = sl + it * W;
+    if (rloc >= kRowsPerBlock || qp >= nq) continue;
     const int sv = s_sh[rloc];
     if (sv < 0) continue;
     const int row = row0 + rloc;
-    const int r4 = 4 * q4;
-    float2 v[4];
+    const int r0 = PC * qp;
+    float2 v[PC];
     if (sv < d) {
       const float2* src = a.W + (size_t)row * d * a.chi_r + (size_t)sv * a.chi_r;
-      if (even && r4 + 4 <= a.chi_r) {
-        const float4 p0 = *reinterpret_cast<const float4*>(src + r4);
-        const float4 p1 = *reinterpret_cast<const float4*>(src + r4 + 2);
-        v[0] = make_float2(p0.x, p0.y);
-        v[1] = make_float2(p0.z, p0.w);
-        v[2] = make_float2(p1.x, p1.y);
-        v[3] = make_float2(p1.z, p1.w);
+      if (even && r0 + PC <= a.chi_r) {
+#pragma unroll
+        for (int jj = 0; jj < PC; jj += 2) {
+          const float4 p = *reinterpret_cast<const float4*>(src + r0 + jj);
+          v[jj] = make_float2(p.x, p.y);
+          v[jj + 1] = make_float2(p.z, p.w);
+        }
       } else {
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) v[jj] = r4 + jj < a.chi_r ? src[r4 + jj] : make_float2(0.f, 0.f);
+        for (int jj = 0; jj < PC; ++jj) v[jj] = r0 + jj < a.chi_r ? src[r0 + jj] : make_float2(0.f, 0.f);
       }
       const float scale = scale_sh[rloc];
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) v[jj] = make_float2(__fmul_rn(v[jj].x, scale), __fmul_rn(v[jj].y, scale));
+      for (int jj = 0; jj < PC; ++jj) v[jj] = make_float2(__fmul_rn(v[jj].x, scale), __fmul_rn(v[jj].y, scale));
     } else {
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) v[jj] = make_float2(0.f, 0.f);
+      for (int jj = 0; jj < PC; ++jj) v[jj] = make_float2(0.f, 0.f);
     }
-    LWriter<OUT>(a, row).put4(r4, v);
+    if constexpr (PC == 8)
+      LWriter<OUT>(a, row).put8(r0, v);
+    else
+      LWriter<OUT>(a, row).put4(r0, v);
   }
   // K padding of the 16-bit operand rows past the written pieces
   for (int k = 0; k < nsteps; ++k) {
     const int rloc = (k * 4 + wv) * G + g;
-    if (rloc < kRowsPerBlock && s_sh[rloc] >= 0) LWriter<OUT>(a, row0 + rloc).pad_from(8 * nq, sl, W);
+    if (rloc < kRowsPerBlock && s_sh[rloc] >= 0) LWriter<OUT>(a, row0 + rloc).pad_from(2 * PC * nq, sl, W);
   }
 }
 
@@ -604,6 +664,25 @@ __global__ void init_f16f8_kernel(const InitProb* probs, const ChunkArgs* chp) {
   }
 }
 
+// fp16f6: Lh as init_lp_kernel<f16_t>; the first record holds the E2M3 code
+// of 1 * 2^8 / 2^6 = 4 (code 24) at position 0 with scale code 127 + 6, the
+// others zeros (scale code 127).
+__global__ void init_f16f6_kernel(const InitProb* probs, const ChunkArgs* chp) {
+  const ChunkArgs ch = *chp;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const InitProb a = probs[blockIdx.y];
+  if (i < ch.rows * a.ld) {
+    const int r = i / a.ld, k = i - r * a.ld;
+    ((f16_t*)a.L)[kblk_off((size_t)r, k, a.ld)] = (f16_t)(k == 0 ? 1.f : 0.f);
+    if ((k & 15) == 0) {
+      uint4* d = reinterpret_cast<uint4*>((unsigned char*)a.Ll + pair_off((size_t)r, k, a.ld));
+      d[0] = make_uint4(k == 0 ? 24u : 0u, 0u, 0u, 0u);
+      d[1] = make_uint4(0u, 0u, k == 0 ? 133u : 127u, 0u);
+    }
+    if (k == 0) a.logp[a.logp_in_call ? ch.c0 + r : r] = 0.0;
+  }
+}
+
 // Operand-sized noise for the tile autotuner's timing launches: values of
 // the magnitude the sweep's operands have (a hash of the index; the timed
 // results are discarded).  kind 0: floats in +-0.05; 1: bf16; 2: fp16, both
@@ -642,6 +721,8 @@ hipError_t launch_init(int form, const InitProb* probs, int nprob, const ChunkAr
       hipLaunchKernelGGL(init_lp_kernel<bf16_t>, grid, dim3(256), 0, s, probs, ch);
     else if (form == kFp16F8)
       hipLaunchKernelGGL(init_f16f8_kernel, grid, dim3(256), 0, s, probs, ch);
+    else if (form == kFp16F6)
+      hipLaunchKernelGGL(init_f16f6_kernel, grid, dim3(256), 0, s, probs, ch);
     else
       hipLaunchKernelGGL(init_lp_kernel<f16_t>, grid, dim3(256), 0, s, probs, ch);
   }
@@ -663,10 +744,14 @@ hipError_t launch_zero_int(int* p, int n, hipStream_t s) {
 template <int OUT>
 void launch_measure_t(bool displaced, int grid_rows, int nprob, const MeasureProb* probs, const ChunkArgs* ch,
                       uint64_t seed, int* nflag, hipStream_t s) {
-  if (displaced)  // one wave per row
-    hipLaunchKernelGGL((measure_kernel<OUT, true>), dim3((grid_rows + 3) / 4, nprob), dim3(256), 0, s, probs, ch,
-                       seed, nflag);
-  else
+  if constexpr (OUT != kOutF16F6) {  // (fp16f6 has no displaced form: the library rejects it)
+    if (displaced) {  // one wave per row
+      hipLaunchKernelGGL((measure_kernel<OUT, true>), dim3((grid_rows + 3) / 4, nprob), dim3(256), 0, s, probs, ch,
+                         seed, nflag);
+      return;
+    }
+  }
+  if (!displaced)
     hipLaunchKernelGGL((measure_rows_kernel<OUT>), dim3((grid_rows + kRowsPerBlock - 1) / kRowsPerBlock, nprob),
                        dim3(256), 0, s, probs, ch, seed, nflag);
 }
@@ -683,6 +768,10 @@ hipError_t launch_measure(int form, const MeasureProb* probs, int nprob, const C
     launch_measure_t<kOutF16x2>(displaced, grid_rows, nprob, probs, ch, seed, nflag, s);
   else if (form == kFp16F8)
     launch_measure_t<kOutF16F8>(displaced, grid_rows, nprob, probs, ch, seed, nflag, s);
+  else if (form == kFp16F6) {
+    if (displaced) return hipErrorInvalidValue;
+    launch_measure_t<kOutF16F6>(false, grid_rows, nprob, probs, ch, seed, nflag, s);
+  }
   else
     launch_measure_t<kOutF16>(displaced, grid_rows, nprob, probs, ch, seed, nflag, s);
   return hipGetLastError();

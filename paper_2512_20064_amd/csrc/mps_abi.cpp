@@ -103,8 +103,10 @@ constexpr double kTuneMargin = 0.02;  // a candidate must beat the defaults by t
 
 int check_options(const mps_options* o) {
   if (o->precision != MPS_FP32 && o->precision != MPS_BF16X3 && o->precision != MPS_FP16 &&
-      o->precision != MPS_FP16X3 && o->precision != MPS_FP16F8)
+      o->precision != MPS_FP16X3 && o->precision != MPS_FP16F8 && o->precision != MPS_FP16F6)
     return fail(MPS_EINVAL, "unknown precision %d", o->precision);
+  if (o->precision == MPS_FP16F6 && o->displace)
+    return fail(MPS_EINVAL, "MPS_FP16F6 has no displaced measurement (its left-vector records need whole 16-K slices)");
   if (o->n_chunk < 0) return fail(MPS_EINVAL, "n_chunk < 0");
   if (o->max_device_bytes < 0) return fail(MPS_EINVAL, "max_device_bytes < 0");
   if (o->emit_n < 0) return fail(MPS_EINVAL, "emit_n < 0");
@@ -120,13 +122,16 @@ int lp_form(int precision) {
   return precision == MPS_BF16X3   ? mps::kBf16x3
          : precision == MPS_FP16X3 ? mps::kFp16x3
          : precision == MPS_FP16F8 ? mps::kFp16F8
+         : precision == MPS_FP16F6 ? mps::kFp16F6
                                    : mps::kFp16;
 }
 // hi + lo operand pairs (a second plane per operand: the low parts, or for
-// MPS_FP16F8 the FP8 pair plane of the same size)
+// MPS_FP16F8 / MPS_FP16F6 the FP8 pair plane or FP6 records of the same size)
 bool is_split(int precision) {
-  return precision == MPS_BF16X3 || precision == MPS_FP16X3 || precision == MPS_FP16F8;
+  return precision == MPS_BF16X3 || precision == MPS_FP16X3 || precision == MPS_FP16F8 || precision == MPS_FP16F6;
 }
+// power-of-two column scales of the site tensor
+bool col_scaled(int precision) { return precision == MPS_FP16F8 || precision == MPS_FP16F6; }
 
 // Largest buffers a chain needs, per sample row (and the packed tensor).
 struct Shape {
@@ -170,7 +175,7 @@ size_t chain_layout(int64_t rows, const Shape& sh, int precision, int64_t nstate
   if (precision != MPS_FP32) {
     b.Bh = take((size_t)sh.bmax * 2);
     if (is_split(precision)) b.Bl = take((size_t)sh.bmax * 2);
-    if (precision == MPS_FP16F8) {
+    if (col_scaled(precision)) {
       b.colscale = take((size_t)sh.csmax * sizeof(float));
       b.colpart = take((size_t)sh.csmax * 16 * sizeof(float));
     }
@@ -632,7 +637,7 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
         if (lowp) {
           const int CP = mps::lp_pad_cols(chr, tile), Kp = mps::lp_pad_k(K);
           T = CP / mps::kPartCols;
-          const bool f8 = o.precision == MPS_FP16F8;
+          const bool f8 = col_scaled(o.precision);
           float* cs = f8 ? (float*)at(bufs[b].colscale) : nullptr;
           mps::PackProb pp{site_A(b, k), at(bufs[b].Bh), split ? at(bufs[b].Bl) : nullptr, K, dk, chr, CP, Kp, cs,
                            f8 ? (float*)at(bufs[b].colpart) : nullptr};
@@ -790,7 +795,7 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
     if (!lowp) return MPS_OK;
     const Step& sp = steps[k];
     MPS_TRY(mark(k, 0, stream));
-    if (form == mps::kFp16F8)
+    if (mps::is_f8f6(form))
       MPS_HIP(mps::launch_colscale((const mps::PackProb*)tp(sp.pack), (const int*)tp(sp.cm_start), sp.nprob,
                                    sp.cm_total, stream),
               "column-scale launch");
@@ -1331,7 +1336,7 @@ int mps_autotune_tiles(mps_handle h, int32_t B, const mps_chain* chains_in, int6
   sz[S_BL] = lowp && is_split(o.precision) ? (size_t)all.bmax * 2 : 0;
   sz[S_W] = (size_t)rows * all.wmax * sizeof(float2);
   sz[S_Q] = (size_t)rows * all.qtmax * sizeof(float);
-  sz[S_CS] = form == mps::kFp16F8 ? (size_t)all.csmax * 17 * sizeof(float) : 0;
+  sz[S_CS] = mps::is_f8f6(form) ? (size_t)all.csmax * 17 * sizeof(float) : 0;
   sz[S_TAB] = 4096;
   size_t total = 0, off[8];
   for (int i = 0; i < 8; ++i) {
@@ -1362,8 +1367,8 @@ int mps_autotune_tiles(mps_handle h, int32_t B, const mps_chain* chains_in, int6
   const int lkind = !lowp ? 0 : form == mps::kBf16x3 ? 1 : 2;
   if (err == MPS_OK) chk(mps::launch_fill_noise(buf + off[S_L], lowp ? sz[S_L] / 2 : sz[S_L] / 4, lkind, 1, stream), "noise");
   if (err == MPS_OK && sz[S_LL])
-    chk(mps::launch_fill_noise(buf + off[S_LL], form == mps::kFp16F8 ? sz[S_LL] : sz[S_LL] / 2,
-                               form == mps::kFp16F8 ? 3 : lkind, 2, stream),
+    chk(mps::launch_fill_noise(buf + off[S_LL], mps::is_f8f6(form) ? sz[S_LL] : sz[S_LL] / 2,
+                               mps::is_f8f6(form) ? 3 : lkind, 2, stream),
         "noise");
   char* const tabd = buf + off[S_TAB];
   const mps::ChunkArgs ca{(int)rows, 0, 0, 0};
@@ -1380,7 +1385,7 @@ int mps_autotune_tiles(mps_handle h, int32_t B, const mps_chain* chains_in, int6
       int tn_total = 0;
       if (lowp) {
         const int CP = mps::lp_pad_cols(chr, v), Kp = mps::lp_pad_k(K);
-        float* cs = form == mps::kFp16F8 ? (float*)(buf + off[S_CS]) : nullptr;
+        float* cs = mps::is_f8f6(form) ? (float*)(buf + off[S_CS]) : nullptr;
         mps::PackProb pp{(const float2*)kv.second, buf + off[S_BH], sz[S_BL] ? buf + off[S_BL] : nullptr,
                          K, dk, chr, CP, Kp, cs, cs ? cs + all.csmax : nullptr};
         mps::ContractLpProb cp{buf + off[S_L], sz[S_LL] ? buf + off[S_LL] : nullptr, pp.Bh, pp.Bl,
@@ -1395,7 +1400,7 @@ int mps_autotune_tiles(mps_handle h, int32_t B, const mps_chain* chains_in, int6
         put(1056, cm, sizeof cm);
         put(1088, &ca, sizeof ca);
         if (!chk(hipMemcpyAsync(tabd, blob.data(), blob.size(), hipMemcpyHostToDevice, stream), "hipMemcpyAsync")) break;
-        if (form == mps::kFp16F8 &&
+        if (mps::is_f8f6(form) &&
             !chk(mps::launch_colscale((const mps::PackProb*)(tabd + 512), (const int*)(tabd + 1056), 1, cm[1], stream),
                  "column-scale launch"))
           break;

@@ -79,7 +79,18 @@ __host__ __device__ inline size_t kblk_off(size_t r, int k, int Kp) {
 // tensor: [B8l | B8h], so that byte p of a row meets byte p of a column in
 // one MFMA: L8h*B8l and L8l*B8h).  A pair plane has the byte size and
 // K-blocking of a 16-bit plane.
-enum LpForm { kBf16x3 = 1, kFp16 = 2, kFp16x3 = 3, kFp16x2 = 4, kFp16F8 = 5 };
+//
+// kFp16F6: kFp16F8 with the correction operands in OCP FP6 E2M3 (3 mantissa
+// bits, values up to 7.5) on the same block-scaled MFMA at twice the FP8
+// rate.  E2M3 spans only 2^-3 .. 7.5, so each 32-value lane record gets its
+// own power-of-two scale s: the record of (row or column, 16-K slice) holds
+// the 32 six-bit codes of the FP8 pair-plane values divided by s (code p at
+// bits 6p .. 6p+5, little-endian over bytes 0 .. 23), then the E8M0 code of
+// s in byte 24 (the site tensor's carries the common 2^-19 as well: code
+// 127 + log2(s) - 19), bytes 25 .. 31 zero.  The MFMA applies a lane's scale
+// to the 32 values that lane holds.
+enum LpForm { kBf16x3 = 1, kFp16 = 2, kFp16x3 = 3, kFp16x2 = 4, kFp16F8 = 5, kFp16F6 = 6 };
+__host__ __device__ inline bool is_f8f6(int form) { return form == kFp16F8 || form == kFp16F6; }
 
 // Byte offset of K value k of row r in a pair plane (high part; the low part
 // is 16 bytes further): the 16-bit K-blocking with one byte per K value.

@@ -16,9 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmps.so")
 
 MPS_OK, MPS_EINVAL, MPS_ENOMEM, MPS_ENODEV, MPS_EHIP, MPS_ENUMERIC = 0, -1, -2, -3, -4, -5
-MPS_FP32, MPS_BF16X3, MPS_FP16, MPS_FP16X3, MPS_FP16F8 = 0, 1, 2, 3, 4
+MPS_FP32, MPS_BF16X3, MPS_FP16, MPS_FP16X3, MPS_FP16F8, MPS_FP16F6 = 0, 1, 2, 3, 4, 5
 PRECISIONS = {"fp32": MPS_FP32, "bf16x3": MPS_BF16X3, "fp16": MPS_FP16, "fp16x3": MPS_FP16X3,
-              "fp16f8": MPS_FP16F8}
+              "fp16f8": MPS_FP16F8, "fp16f6": MPS_FP16F6}
 MPS_C64, MPS_CF16, MPS_CF8 = 0, 1, 2
 STORAGE = {"c64": MPS_C64, "cf16": MPS_CF16, "cf8": MPS_CF8}
 

@@ -18,7 +18,7 @@ def _ensemble(n, seed=2):
     return chains
 
 
-@pytest.mark.parametrize("form", ["fp32", "bf16x3", "fp16", "fp16x3", "fp16f8"])
+@pytest.mark.parametrize("form", ["fp32", "bf16x3", "fp16", "fp16x3", "fp16f8", "fp16f6"])
 def test_batch_equals_single_chain_calls(form):
     """Chain b of a batch is bit-identical to mps_sample on chain b with mps_id = b."""
     from paper_2512_20064_amd import mps

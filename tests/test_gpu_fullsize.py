@@ -18,11 +18,11 @@ CHUNK = 65536
 SEED = 1003
 
 
-EPS = {"fp32": 1e-5, "bf16x3": 1e-3, "fp16x3": 1e-3, "fp16f8": 1e-3}
+EPS = {"fp32": 1e-5, "bf16x3": 1e-3, "fp16x3": 1e-3, "fp16f8": 1e-3, "fp16f6": 1e-3}
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("form", ["fp32", "bf16x3", "fp16x3", "fp16f8"])
+@pytest.mark.parametrize("form", ["fp32", "bf16x3", "fp16x3", "fp16f8", "fp16f6"])
 def test_resident_chain_sampled_rows(form):
     from paper_2512_20064_amd import mps
     from tests.parity_util import compare

@@ -47,7 +47,7 @@ def _assert_prefix_dependent(ref, seed, outcomes, rows, sites, n_index=None):
     return spreads
 
 
-@pytest.mark.parametrize("form", ["fp16x3", "bf16x3", "fp16f8"])
+@pytest.mark.parametrize("form", ["fp16x3", "bf16x3", "fp16f8", "fp16f6"])
 def test_chi10000_streamed_window_prefix_parity(form):
     """fp16x3 runs two MFMA products per complex product on these fp16-exact
     sites (the streamed workload's default); bf16x3 runs three."""
@@ -96,7 +96,7 @@ def test_chi10000_streamed_window_prefix_parity(form):
     print("prefix call", rep, flush=True)
 
 
-@pytest.mark.parametrize("form", ["bf16x3", "fp16f8"])
+@pytest.mark.parametrize("form", ["bf16x3", "fp16f8", "fp16f6"])
 def test_uneven_chain_prefix_parity(form):
     from paper_2512_20064_amd import mps
     from tests.parity_util import compare

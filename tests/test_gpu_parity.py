@@ -31,12 +31,13 @@ def mpsmod():
 # small-bond kernel (FP32 in every form); "fp32-steps" and the 16-bit forms
 # here force the per-site launches, so that the 16-bit kernels are the ones
 # tested on small chains too.
-FORMS = ["fp32", "fp32-steps", "bf16x3", "fp16", "fp16x3", "fp16f8"]
+FORMS = ["fp32", "fp32-steps", "bf16x3", "fp16", "fp16x3", "fp16f8", "fp16f6"]
 # Forms held to the stated probability bars (FP32 1e-5, low precision 1e-3).
 # The single-product fp16 form does not meet 1e-3 beyond a few sites; its
 # error is measured against a looser derived bound in test_fp16_error_report.
-PARITY_FORMS = ["fp32", "fp32-steps", "bf16x3", "fp16x3", "fp16f8"]
-EPS = {"fp32": 1e-5, "fp32-steps": 1e-5, "bf16x3": 1e-3, "fp16": 1e-3, "fp16x3": 1e-3, "fp16f8": 1e-3}
+PARITY_FORMS = ["fp32", "fp32-steps", "bf16x3", "fp16x3", "fp16f8", "fp16f6"]
+EPS = {"fp32": 1e-5, "fp32-steps": 1e-5, "bf16x3": 1e-3, "fp16": 1e-3, "fp16x3": 1e-3, "fp16f8": 1e-3,
+       "fp16f6": 1e-3}
 
 
 def _sampler(mpsmod, form, **kw):
@@ -268,6 +269,12 @@ def test_displacement_parity(mpsmod, form):
     rng = np.random.default_rng(5)
     mu = ((rng.standard_normal((N, M)) + 1j * rng.standard_normal((N, M))) * 0.4).astype(np.complex64)
     s = _sampler(mpsmod, form)
+    if form == "fp16f6":  # no displaced form: an argument error before any launch
+        with pytest.raises(mpsmod.MPSError) as e:
+            s.sample(upload(t), N, 11, displace=torch.from_numpy(mu).cuda())
+        assert e.value.code == mpsmod.MPS_EINVAL
+        s.close()
+        return
     r = s.sample(upload(t), N, 11, emit_n=N, displace=torch.from_numpy(mu).cuda())
     torch.cuda.synchronize()
     g = {k: r[k].cpu().numpy() for k in ("outcomes", "logp", "probs", "u")}
@@ -335,11 +342,12 @@ def test_small_bond_kernel_runs_and_agrees_with_per_site_launches(mpsmod):
     c.close()
 
 
-@pytest.mark.parametrize("form", ["fp16f8", "bf16x3"])
+@pytest.mark.parametrize("form", ["fp16f8", "fp16f6", "bf16x3"])
 def test_power_of_two_site_scaling_is_exact(mpsmod, form):
     """Every site multiplied by 2^-20 or 2^12 (a non-canonical input that the
-    sampler normalises by S): fp16f8 absorbs the factor into its per-column
-    power-of-two scales and bf16 keeps FP32's exponent range, so W, the
+    sampler normalises by S): fp16f8 and fp16f6 absorb the factor into their
+    per-column power-of-two scales (fp16f6's record scales see the same
+    values) and bf16 keeps FP32's exponent range, so W, the
     branch weights and S scale by exact powers of two and the outcomes, logp
     and conditional probabilities are bit-identical to the unscaled run."""
     _say(f"power-of-two site scaling {form}")

@@ -54,7 +54,7 @@ def _stored(tensors, kind, where):
 CASES = [("c64", "host"), ("cf16", "device"), ("cf16", "host"), ("cf8", "device"), ("cf8", "mixed")]
 
 
-@pytest.mark.parametrize("form", ["fp32", "bf16x3", "fp16x3", "fp16f8"])
+@pytest.mark.parametrize("form", ["fp32", "bf16x3", "fp16x3", "fp16f8", "fp16f6"])
 @pytest.mark.parametrize("kind,where", CASES)
 def test_staged_equals_resident_expanded_tensor(form, kind, where):
     """A staged call is bit-identical to a device-resident complex64 call on

@@ -47,7 +47,7 @@ def _mixed_chain():
     return synth.to_c64(synth.random_mps(31, dl, chi)), dl, chi
 
 
-@pytest.mark.parametrize("form", ["fp32", "bf16x3", "fp16x3", "fp16f8", "fp16"])
+@pytest.mark.parametrize("form", ["fp32", "bf16x3", "fp16x3", "fp16f8", "fp16f6", "fp16"])
 def test_tile_choices_are_bit_identical(form, tmp_path):
     """Every site shape on the wide tile, every one on the narrow tile, and the
     tuner's choice give the same outcomes, logp and conditional
@@ -90,7 +90,7 @@ def test_tile_choices_are_bit_identical(form, tmp_path):
     s2.close()
 
 
-@pytest.mark.parametrize("form", ["fp32", "bf16x3", "fp16f8"])
+@pytest.mark.parametrize("form", ["fp32", "bf16x3", "fp16f8", "fp16f6"])
 def test_narrow_tiles_match_the_oracle(form):
     """The narrow tiles on their own against the FP64 oracle (forced prefix)."""
     from paper_2512_20064_amd import mps

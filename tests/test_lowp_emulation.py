@@ -20,6 +20,14 @@ site tensor is complex64.
            Bl * 2^11 rounded to E4M3 as they are, the left vector's parts
            with fixed scales (its entries are at most 1 in magnitude after
            renormalisation: hi times 2^8, lo times 2^19).
+  f16f6    f16f8 with the correction operands in OCP FP6 E2M3 (3 mantissa
+           bits, magnitudes 2^-3 .. 7.5).  The operands are the real
+           embedding the GPU contracts (interleaved re, im along K; site
+           columns (Re a, -Im a) and (Im a, Re a)), and every record of 16
+           real K of a row or column, its 16 high-part and 16 low-part
+           values together, is divided by its own power of two (the smallest
+           that brings its largest magnitude to at most 7.5) before rounding
+           to E2M3 (nearest, ties to even).
 
 The conditionals p_k(i | prefix) of each emulated path are compared with the
 oracle's along the same path.
@@ -46,6 +54,40 @@ def _f16(x):
 
 def _e4m3(x):
     return E4M3[synth.encode_e4m3(x)].astype(np.float32)
+
+
+def _e2m3(x):
+    """Round to the nearest OCP E2M3 value, ties to even; saturates at 7.5."""
+    x = np.asarray(x, dtype=np.float64)
+    a = np.minimum(np.abs(x), 7.5)
+    _, e2 = np.frexp(np.where(a > 0, a, 1.0))        # a in [2^(e2-1), 2^e2)
+    step = np.where(a < 1.0, 0.125, 2.0 ** (e2 - 1 - 3))  # 3 mantissa bits; subnormal step 1/8
+    return np.sign(x) * np.minimum(np.rint(a / step) * step, 7.5)
+
+
+def _e2m3_records(v):
+    """v [..., 32]: each record divided by its power of two s (smallest with
+    max|v| / s <= 7.5), rounded to E2M3, multiplied back."""
+    amax = np.abs(v).max(axis=-1, keepdims=True)
+    _, e = np.frexp(np.where(amax > 0, amax, 1.0))   # amax = m 2^e, m in [0.5, 1)
+    k = np.where(amax / 2.0 ** (e - 3) <= 7.5, e - 3, e - 2)
+    s = 2.0 ** k
+    return _e2m3(v / s) * s
+
+
+def _embed_k(z):
+    """Real K of a complex vector (or of the rows of a matrix): (re, im) interleaved."""
+    r = np.empty((2 * z.shape[0],) + z.shape[1:])
+    r[0::2], r[1::2] = z.real, z.imag
+    return r
+
+
+def _records(v, ns):
+    """Records of 16 real K over axis 0 of v [2K(, cols)], padded to ns slices:
+    shape [(cols,) ns, 16]."""
+    pad = np.zeros((16 * ns,) + v.shape[1:])
+    pad[:v.shape[0]] = v
+    return np.transpose(pad.reshape(ns, 16, -1), (2, 0, 1)) if v.ndim > 1 else pad.reshape(ns, 16)
 
 
 def _cplx(f, z):
@@ -75,6 +117,21 @@ def _split_site(B, form):
         h8 = _cplx(_e4m3, hi)
         l8 = _cplx(_e4m3, lo * 2.0 ** 11) * 2.0 ** -11
         return hi, (h8, l8, sc)
+    if form == "f16f6":
+        amax = np.maximum(np.abs(B.real), np.abs(B.imag)).max(axis=0)
+        sc = _pow2_scale(amax)
+        Bs = (B / sc).astype(np.complex64)
+        hi = _cplx(_f16, Bs)
+        lo = (Bs - hi).astype(np.complex64)
+        ns = (2 * B.shape[0] + 15) // 16
+        # real columns p = 0 (Re W) and p = 1 (Im W) of each complex column
+        rec = []
+        for emb in (lambda z: _embed_k(z.conj()), lambda z: _embed_k(1j * z.conj())):
+            # p = 0: (Re a, -Im a) = embed(conj a); p = 1: (Im a, Re a) = embed(i conj a)
+            r = np.concatenate([_records(emb(lo.astype(complex)) * 2.0 ** 11, ns),
+                                _records(emb(hi.astype(complex)), ns)], axis=-1)  # [cols, ns, 32]: [lo | hi]
+            rec.append(_e2m3_records(r))
+        return hi, (rec, ns, sc)
     raise ValueError(form)
 
 
@@ -90,6 +147,12 @@ def _contract(l, parts, form):
         return _cplx(_f16, l).astype(complex) @ hi
     lh = _cplx(_f16, l)
     ll = (l - lh).astype(np.complex64)
+    if form == "f16f6":
+        rec, ns, sc = rest
+        a = _e2m3_records(np.concatenate([_records(_embed_k(lh.astype(complex)) * 2.0 ** 8, ns),
+                                          _records(_embed_k(ll.astype(complex)) * 2.0 ** 19, ns)], axis=-1))
+        corr = [np.einsum("sj,csj->c", a, r) * 2.0 ** -19 for r in rec]  # [hi | lo] meets [lo | hi]
+        return (lh.astype(complex) @ hi + corr[0] + 1j * corr[1]) * sc
     lh8 = _cplx(_e4m3, lh * 2.0 ** 8) * 2.0 ** -8
     ll8 = _cplx(_e4m3, ll * 2.0 ** 19) * 2.0 ** -19
     h8, l8, sc = rest
@@ -138,10 +201,11 @@ def test_fp8_corrections_meet_the_low_precision_bar(chain):
     """fp16 hi products plus FP8 correction products stay well inside 1e-3
     over 128 sites at chi = 64 (the same chain takes bf16x3 to a few 1e-5),
     while the single fp16 product does not."""
-    e = {f: _max_err(chain, 5, 24, f) for f in ("bf16x3", "f16f8", "fp16")}
+    e = {f: _max_err(chain, 5, 24, f) for f in ("bf16x3", "f16f8", "f16f6", "fp16")}
     print(e)
     assert e["bf16x3"] < 2e-4
     assert e["f16f8"] < 5e-4
+    assert e["f16f6"] < 5e-4
     assert e["fp16"] > 1e-3
 
 
@@ -155,3 +219,4 @@ def test_fp8_corrections_with_scaled_site_tensor():
     for sc in (2.0 ** -20, 2.0 ** 10):
         t = [np.ascontiguousarray(x * np.float32(sc)) for x in base]
         assert _max_err(t, 6, 12, "f16f8") < 5e-4, sc
+        assert _max_err(t, 6, 12, "f16f6") < 5e-4, sc
