@@ -8,12 +8,14 @@ GBS-shaped resident chain, M = 1024 sites, d = 4, chi = 1024 (bond ramp
 (one device buffer per site, 32 GiB), 65536 samples per step; step s draws
 global samples [s*65536, (s+1)*65536) of the N = 2^20 job.
 
-Prints one JSON line: site-samples/s of the split-precision form (bf16 hi+lo,
-three MFMA products, within 1e-3 of the FP64 oracle), the contraction kernel
-against the MFMA roofline of its operand type (event-timed live over the
-timed region; algorithmic flops, with the issued MFMA rate of the split form
-beside), the plain FP32 path timed beside it, and the FP64 oracle timed
-on the host cores on a bounded sample of the same chain.
+Prints one JSON line: site-samples/s of the low-precision headline form
+(fp16f6: the fp16 product of the high parts plus both correction products in
+FP6 E2M3 with per-record power-of-two scales, within 1e-3 of the FP64
+oracle), the contraction kernel against the MFMA roofline of its operand
+type (event-timed live over the timed region; algorithmic flops, with the
+issued MFMA rate in fp16-product equivalents beside), the fp16f8, bf16x3 and
+plain FP32 forms timed beside it, and the FP64 oracle timed on the host
+cores on a bounded sample of the same chain.
 
 Other workloads (one JSON line each, not the headline):
   --workload uneven   M = 2048, d_k in {2..6}, chi_k = min(prod d, 4096),
@@ -564,8 +566,8 @@ def run_batch_bench(args):
 
 
 WORKLOAD_DEFAULTS = {
-    "resident": {"sites": 1024, "chi": 1024, "pool": 16, "chunk": 65536, "precision": "fp16f8",
-                 "beside": "bf16x3,fp32"},
+    "resident": {"sites": 1024, "chi": 1024, "pool": 16, "chunk": 65536, "precision": "fp16f6",
+                 "beside": "fp16f8,bf16x3,fp32"},
     "small": {"sites": 32, "chi": 32, "pool": 1, "chunk": 4096, "precision": "fp32", "beside": ""},
     "uneven": {"sites": 2048, "chi": 4096, "pool": 2, "chunk": 8192, "precision": "bf16x3", "beside": ""},
     # N = 2^20 as configured; 24 sites (7 ramp, 17 plateau) keep one call,

@@ -12,33 +12,27 @@ namespace mps {
 constexpr float kE2M3Max = 7.5f;
 
 // Code of x rounded to nearest, ties to even mantissa, for |x| <= 7.5 (the
-// caller's scale guarantees it; larger magnitudes saturate to 7.5).
-__device__ inline unsigned e2m3_code(float x) {
-  const unsigned sgn = x < 0.f ? 32u : 0u;
-  const float a = fabsf(x);
-  if (!(a < kE2M3Max)) return sgn | 31u;  // 7.5 (and NaN, which the fp16 product carries anyway)
-  if (a < 1.f) return sgn | (unsigned)rintf(a * 8.f);  // 0..8; 8 is 1.0 (exponent 1, mantissa 0)
-  int e2;
-  (void)frexpf(a, &e2);  // a = f * 2^e2, f in [0.5, 1): a in [2^(e2-1), 2^e2)
-  const int E = e2 - 1;  // 0, 1 or 2
-  unsigned m8 = (unsigned)rintf(ldexpf(a, 3 - E));  // 8 .. 16
-  unsigned Ef = (unsigned)E + 1u;
-  if (m8 == 16u) {
-    m8 = 8u;
-    Ef += 1u;
-  }
-  if (Ef > 3u) {
-    Ef = 3u;
-    m8 = 15u;
-  }
-  return sgn | (Ef << 3) | (m8 - 8u);
+// caller's scale guarantees it; larger magnitudes and NaN saturate to 7.5).
+// From |x| >= 1 the code is the FP32 bit pattern rounded to 3 mantissa bits
+// (adding 2^19 - 1 plus the kept lowest bit rounds ties to even), with the
+// exponent field rebased (127 + E becomes E + 1); a carry out of the
+// mantissa bumps the exponent as it should.  Below 1 the values are the
+// multiples of 1/8 (subnormal codes 0 .. 7; 8 is 1.0).
+__host__ __device__ inline unsigned e2m3_code(float x) {
+  const unsigned u = __builtin_bit_cast(unsigned, x);
+  const unsigned sgn = (u >> 26) & 32u;
+  const float a = fminf(__builtin_bit_cast(float, u & 0x7FFFFFFFu), kE2M3Max);
+  const unsigned au = __builtin_bit_cast(unsigned, a);
+  const unsigned cn = ((au + 0x7FFFFu + ((au >> 20) & 1u)) >> 20) - (126u << 3);
+  const unsigned cs = (unsigned)rintf(a * 8.f);
+  return sgn | (a < 1.f ? cs : cn);
 }
 
 // Smallest k with amax / 2^k <= 7.5, clamped to [-126, 127] (0 for a zero
 // or non-finite amax; a non-finite value still reaches W through the fp16
 // product of the high parts).
-__device__ inline int e2m3_scale_exp(float amax) {
-  if (!(amax > 0.f) || isinf(amax)) return 0;
+__host__ __device__ inline int e2m3_scale_exp(float amax) {
+  if (!(amax > 0.f && amax <= 3.40282347e38f)) return 0;  // zero, NaN, infinity
   int E;
   const float m = frexpf(amax, &E);  // amax = m * 2^E, m in [0.5, 1); 7.5 = 0.9375 * 2^3
   int k = m <= 0.9375f ? E - 3 : E - 2;
