@@ -73,14 +73,15 @@ def kernel_hash(form) -> str:
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def traffic_for(form, chunk):
+def traffic_for(form, chunk, chi):
     """HBM bytes per launch of the contraction from committed counter runs,
-    or None if they were taken on another version of the kernel."""
+    or None if they were taken on another version of the kernel or another
+    launch shape (chunk rows, bond dimension)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{form}.json")
     if not os.path.exists(path):
         return None
     tr = json.load(open(path))
-    if tr.get("kernel_sha") != kernel_hash(form) or tr.get("chunk") != chunk:
+    if tr.get("kernel_sha") != kernel_hash(form) or tr.get("chunk") != chunk or tr.get("chi") != chi:
         return None
     return tr.get("bytes_per_launch")
 
@@ -230,7 +231,7 @@ def cpu_baseline(t128, seed, n_samples, n_sites, n_samples_1t):
             "host": hi}
 
 
-def roofline_of(form, c_fl, c_n, c_ms, dt, m_ms, p_ms, chunk, products=None):
+def roofline_of(form, c_fl, c_n, c_ms, dt, m_ms, p_ms, chunk, chi, products=None):
     """Roofline of the contraction kernel: algorithmic flops (8 d chi_l chi_r
     per site-sample, the complex contraction itself) per launch over the
     event-timed average launch, against the dense MFMA peak of the operand
@@ -243,7 +244,7 @@ def roofline_of(form, c_fl, c_n, c_ms, dt, m_ms, p_ms, chunk, products=None):
     issued = alg * products
     return {
         "bound": "mfma", "achieved": round(alg, 2), "peak": f["peak"], "unit": "TFLOP/s",
-        "frac": round(alg / f["peak"], 4), "traffic": traffic_for(form, chunk),
+        "frac": round(alg / f["peak"], 4), "traffic": traffic_for(form, chunk, chi),
         "kernel": f["kernel"] if products == f["mfma_per_alg"] else f["kernel"].replace(",3>", f",{products}>"),
         "alg_flops_per_launch": round(c_fl / c_n),
         "mfma_issued": {"tflops": round(issued, 2), "frac": round(issued / f["peak"], 4),
@@ -355,7 +356,7 @@ def run_chain_bench(args):
         out = {"value": args.chunk * M * steps / dt, "ms_per_step": dt / steps * 1e3, "dt": dt,
                "alg_tflops": (c_fl + f_fl) / dt / 1e12}
         if not args.no_profile and c_ms > 0:
-            out["roofline"] = roofline_of(form, c_fl, c_n, c_ms, dt, m_ms, p_ms, args.chunk)
+            out["roofline"] = roofline_of(form, c_fl, c_n, c_ms, dt, m_ms, p_ms, args.chunk, args.chi)
         elif not args.no_profile and f_ms > 0:
             out["roofline"] = roofline_small(f_fl, f_n, f_ms, dt)
         return out
@@ -480,7 +481,7 @@ def run_stream_bench(args):
         # scales (the encoder's choice), expand to values exact in fp16: the
         # fp16 split form skips the product with the (zero) low parts
         "roofline": (roofline_of(args.precision, st.contract_flops, st.contract_launches, st.contract_ms,
-                                 dt, st.measure_ms, st.pack_ms, args.chunk,
+                                 dt, st.measure_ms, st.pack_ms, args.chunk, args.chi,
                                  products=2 if (args.precision == "fp16x3" and kind in ("cf16", "cf8")) else None)
                      if st.contract_ms > 0 else None),
         "cpu_baseline": None,

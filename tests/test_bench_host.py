@@ -15,7 +15,7 @@ import bench  # noqa: E402
 
 def test_roofline_reports_algorithmic_flops_against_the_operand_peak():
     # 10 launches of 1e14 algorithmic flops in 1000 ms: 1 PFLOP/s
-    r = bench.roofline_of("bf16x3", 1e15, 10, 1000.0, 2.0, 10.0, 1.0, 65536)
+    r = bench.roofline_of("bf16x3", 1e15, 10, 1000.0, 2.0, 10.0, 1.0, 65536, 1024)
     assert r["bound"] == "mfma" and r["unit"] == "TFLOP/s"
     assert r["achieved"] == pytest.approx(1000.0)
     assert r["peak"] == 2516.6 and r["frac"] == pytest.approx(1000.0 / 2516.6, abs=1e-4)
@@ -24,23 +24,24 @@ def test_roofline_reports_algorithmic_flops_against_the_operand_peak():
     assert r["mfma_issued"]["products_per_complex_product"] == 3
     assert r["avg_launch_ms"] == pytest.approx(100.0) and r["launches"] == 10
     assert r["time_share"]["contract"] == pytest.approx(0.5)
-    f = bench.roofline_of("fp32", 1e15, 10, 1000.0, 2.0, 10.0, 1.0, 65536)
+    f = bench.roofline_of("fp32", 1e15, 10, 1000.0, 2.0, 10.0, 1.0, 65536, 1024)
     assert f["peak"] == 157.3 and f["mfma_issued"]["tflops"] == pytest.approx(f["achieved"])
-    two = bench.roofline_of("fp16x3", 1e15, 10, 1000.0, 2.0, 10.0, 1.0, 65536, products=2)
+    two = bench.roofline_of("fp16x3", 1e15, 10, 1000.0, 2.0, 10.0, 1.0, 65536, 1024, products=2)
     assert two["kernel"] == "contract_lp_kernel<f16,2>" and two["mfma_issued"]["tflops"] == pytest.approx(2000.0)
 
 
 def test_traffic_record_is_ignored_for_another_kernel_version(tmp_path, monkeypatch):
-    rec = {"kernel_sha": bench.kernel_hash("bf16x3"), "chunk": 65536, "bytes_per_launch": 123}
+    rec = {"kernel_sha": bench.kernel_hash("bf16x3"), "chunk": 65536, "chi": 1024, "bytes_per_launch": 123}
     (tmp_path / "profiles").mkdir()
     (tmp_path / "profiles" / "traffic_bf16x3.json").write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "kernel_hash", lambda form: rec["kernel_sha"])
-    assert bench.traffic_for("bf16x3", 65536) == 123
-    assert bench.traffic_for("bf16x3", 32768) is None  # taken at another chunk
+    assert bench.traffic_for("bf16x3", 65536, 1024) == 123
+    assert bench.traffic_for("bf16x3", 32768, 1024) is None  # taken at another chunk
+    assert bench.traffic_for("bf16x3", 65536, 10000) is None  # taken at another bond dimension
     monkeypatch.setattr(bench, "kernel_hash", lambda form: "0" * 16)
-    assert bench.traffic_for("bf16x3", 65536) is None  # source changed since
-    assert bench.traffic_for("fp32", 65536) is None  # no record
+    assert bench.traffic_for("bf16x3", 65536, 1024) is None  # source changed since
+    assert bench.traffic_for("fp32", 65536, 1024) is None  # no record
 
 
 def test_more_than_one_gpu_is_refused():
