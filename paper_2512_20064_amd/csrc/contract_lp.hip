@@ -199,6 +199,15 @@ __device__ inline void store_partials(const floatx16 (&acc)[2][4], float* red, i
   }
 }
 
+// W element store: a global-memory (not flat) store marked nontemporal.  W
+// is written once per launch and read back by the measurement only for the
+// chosen branch, long after the 2 GiB of a plateau launch has left the
+// caches, so its lines need not displace operand tiles in L2 (1-4 % per
+// launch, standalone timing of the headline shape).
+__device__ inline void store_w(float* p, float x) {
+  __builtin_nontemporal_store(x, (__attribute__((address_space(1))) float*)p);
+}
+
 // Pipeline: stage kt lives in LDS buffer kt % NST.  Operand tiles go straight
 // from memory into LDS (global_load_lds_dwordx4: no staging registers and no
 // LDS store phase), NST-1 stages ahead of the stage being read from LDS,
@@ -384,7 +393,7 @@ __global__ __launch_bounds__(LpTile<NWC>::NTHR, 1) void contract_lp_kernel(const
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const int gr = m0 + wr + rb * 32 + (v >> 2) * 8 + half * 4 + (v & 3);
-          if (gr < rows) Wf[(size_t)gr * wpitch + fcol] = acc[rb][cb][v];
+          if (gr < rows) store_w(Wf + (size_t)gr * wpitch + fcol, acc[rb][cb][v]);
         }
       }
     }
@@ -812,7 +821,7 @@ __device__ inline void contract_f16f8_body(const ContractLpProb* probs, const in
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const int gr = m0 + wr + rb * 32 + (v >> 2) * 8 + half * 4 + (v & 3);
-          if (gr < rows) Wf[(size_t)gr * wpitch + fcol] = acc[rb][cb][v];
+          if (gr < rows) store_w(Wf + (size_t)gr * wpitch + fcol, acc[rb][cb][v]);
         }
       }
     }
