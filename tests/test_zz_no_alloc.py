@@ -53,6 +53,7 @@ CASES = [
     ("bf16x3", 1, (7, 20, 4, 64, 3000), (8, 12, 4, 40, 900)),
     ("fp16x3", 1, (9, 16, 3, 96, 2048), (10, 9, 2, 64, 257)),
     ("fp16f8", 1, (13, 14, 4, 128, 2048), (14, 9, 3, 64, 300)),
+    ("fp16f6", 1, (15, 14, 4, 128, 2048), (16, 9, 3, 64, 300)),
 ]
 
 
