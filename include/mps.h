@@ -85,9 +85,7 @@ enum {
                         instruction at twice the FP8 rate: 1.5 fp16-product
                         equivalents per complex product.  E2M3's range is narrow,
                         so every 32 correction values of a row (column) and 16-K
-                        slice carry their own power-of-two scale.  No displaced
-                        measurement: mps_options.displace must be NULL
-                        (MPS_EINVAL otherwise).                                   */
+                        slice carry their own power-of-two scale.                 */
 };
 
 /* Storage of the site tensors (Section 3.3.2: tensors stored and moved in

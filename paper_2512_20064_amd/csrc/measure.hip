@@ -233,7 +233,8 @@ struct LWriter<kOutF16F8> {
 // record of the 32 values Lh * 2^8 (codes 0..15) and (x - Lh) * 2^19 (codes
 // 16..31) divided by the record's power of two 2^k (E8M0 code 127 + k in
 // byte 24).  A record needs the whole slice, so this writer takes pieces of
-// 8 complex (put8) and the measurement never hands it single values.
+// 8 complex (put8) and the measurement never hands it single values (the
+// displaced measurement forms whole slices for it too).
 template <>
 struct LWriter<kOutF16F6> {
   uint32_t* hi;
@@ -429,7 +430,42 @@ __global__ __launch_bounds__(256) void measure_kernel(const MeasureProb* probs, 
 
   const float2* src = Wrow + (size_t)s * a.chi_r;
   LWriter<OUT> out(a, row);
-  if (ok && !disp) {
+  if constexpr (OUT == kOutF16F6) {
+    // The record writer takes whole 16-K slices: each lane forms 8 complex
+    // values of the chosen branch (of W' = D(mu) W when displaced; zeros past
+    // chi_r and for a flagged sample), the same arithmetic per value as the
+    // other writers' paths below.
+    const float scale = ok ? (float)(1.0 / sqrt(qs)) : 0.f;
+    const float2* Ds = Dsh[wv] + s * d;
+    const int n8 = (a.chi_r + 7) >> 3;
+    for (int q8 = sl; q8 < n8; q8 += W) {
+      float2 v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int r = 8 * q8 + e;
+        float xr = 0.f, xi = 0.f;
+        if (ok && r < a.chi_r) {
+          if (disp) {
+            for (int jj = 0; jj < d; ++jj) {
+              const float2 g = Ds[jj], w = Wrow[(size_t)jj * a.chi_r + r];
+              xr += g.x * w.x - g.y * w.y;
+              xi += g.x * w.y + g.y * w.x;
+            }
+          } else {
+            const float2 w = src[r];
+            xr = w.x;
+            xi = w.y;
+          }
+          xr = __fmul_rn(xr, scale);
+          xi = __fmul_rn(xi, scale);
+        }
+        v[e] = make_float2(xr, xi);
+      }
+      out.put8(8 * q8, v);
+    }
+    out.pad_from(16 * n8, sl, W);
+    return;
+  } else if (ok && !disp) {
     // Each lane takes 4 consecutive complex of the chosen branch (zeros past
     // chi_r), so the 16-bit formats get whole 16-byte stores.
     const float scale = (float)(1.0 / sqrt(qs));
@@ -471,7 +507,7 @@ __global__ __launch_bounds__(256) void measure_kernel(const MeasureProb* probs, 
   } else {
     for (int r = sl; r < a.chi_r; r += W) out.put(r, 0.f, 0.f);
   }
-  out.pad(a, sl, W);
+  if constexpr (OUT != kOutF16F6) out.pad(a, sl, W);
 }
 
 // Measurement without displacement, in two phases per workgroup of 64 rows:
@@ -744,14 +780,10 @@ hipError_t launch_zero_int(int* p, int n, hipStream_t s) {
 template <int OUT>
 void launch_measure_t(bool displaced, int grid_rows, int nprob, const MeasureProb* probs, const ChunkArgs* ch,
                       uint64_t seed, int* nflag, hipStream_t s) {
-  if constexpr (OUT != kOutF16F6) {  // (fp16f6 has no displaced form: the library rejects it)
-    if (displaced) {  // one wave per row
-      hipLaunchKernelGGL((measure_kernel<OUT, true>), dim3((grid_rows + 3) / 4, nprob), dim3(256), 0, s, probs, ch,
-                         seed, nflag);
-      return;
-    }
-  }
-  if (!displaced)
+  if (displaced)  // one wave per row
+    hipLaunchKernelGGL((measure_kernel<OUT, true>), dim3((grid_rows + 3) / 4, nprob), dim3(256), 0, s, probs, ch,
+                       seed, nflag);
+  else
     hipLaunchKernelGGL((measure_rows_kernel<OUT>), dim3((grid_rows + kRowsPerBlock - 1) / kRowsPerBlock, nprob),
                        dim3(256), 0, s, probs, ch, seed, nflag);
 }
@@ -768,10 +800,8 @@ hipError_t launch_measure(int form, const MeasureProb* probs, int nprob, const C
     launch_measure_t<kOutF16x2>(displaced, grid_rows, nprob, probs, ch, seed, nflag, s);
   else if (form == kFp16F8)
     launch_measure_t<kOutF16F8>(displaced, grid_rows, nprob, probs, ch, seed, nflag, s);
-  else if (form == kFp16F6) {
-    if (displaced) return hipErrorInvalidValue;
-    launch_measure_t<kOutF16F6>(false, grid_rows, nprob, probs, ch, seed, nflag, s);
-  }
+  else if (form == kFp16F6)
+    launch_measure_t<kOutF16F6>(displaced, grid_rows, nprob, probs, ch, seed, nflag, s);
   else
     launch_measure_t<kOutF16>(displaced, grid_rows, nprob, probs, ch, seed, nflag, s);
   return hipGetLastError();

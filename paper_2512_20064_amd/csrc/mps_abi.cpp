@@ -105,8 +105,6 @@ int check_options(const mps_options* o) {
   if (o->precision != MPS_FP32 && o->precision != MPS_BF16X3 && o->precision != MPS_FP16 &&
       o->precision != MPS_FP16X3 && o->precision != MPS_FP16F8 && o->precision != MPS_FP16F6)
     return fail(MPS_EINVAL, "unknown precision %d", o->precision);
-  if (o->precision == MPS_FP16F6 && o->displace)
-    return fail(MPS_EINVAL, "MPS_FP16F6 has no displaced measurement (its left-vector records need whole 16-K slices)");
   if (o->n_chunk < 0) return fail(MPS_EINVAL, "n_chunk < 0");
   if (o->max_device_bytes < 0) return fail(MPS_EINVAL, "max_device_bytes < 0");
   if (o->emit_n < 0) return fail(MPS_EINVAL, "emit_n < 0");

@@ -92,24 +92,18 @@ def test_null_handle_and_options(lib):
     lib.mps_destroy(None)  # ignored
 
 
-def test_fp16f6_rejects_displacement_on_host():
-    """MPS_FP16F6 has no displaced measurement: a displacement pointer is an
-    argument error at mps_create and mps_set_options; without it the form is
-    accepted."""
-    o = mps.mps_options_init()
-    o.precision = mps.MPS_FP16F6
-    h = mps.mps_create(0, o)
-    try:
-        o.displace = 256  # never dereferenced: the check comes first
-        with pytest.raises(mps.MPSError) as e:
+def test_every_precision_form_is_accepted_with_and_without_displacement():
+    """The five forms are valid options, with or without a displacement
+    pointer (the pointer is only read by a sampling call)."""
+    for prec in (mps.MPS_FP32, mps.MPS_BF16X3, mps.MPS_FP16, mps.MPS_FP16X3, mps.MPS_FP16F8, mps.MPS_FP16F6):
+        o = mps.mps_options_init()
+        o.precision = prec
+        h = mps.mps_create(0, o)
+        try:
+            o.displace = 256
             mps.mps_set_options(h, o)
-        assert e.value.code == mps.MPS_EINVAL and "MPS_FP16F6" in mps.mps_last_error()
-        with pytest.raises(mps.MPSError):
-            mps.mps_create(0, o)
-        o.precision = mps.MPS_FP16F8
-        mps.mps_set_options(h, o)
-    finally:
-        mps.mps_destroy(h)
+        finally:
+            mps.mps_destroy(h)
 
 
 def test_empty_batch_is_ok_without_work():
