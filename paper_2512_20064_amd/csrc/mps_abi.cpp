@@ -138,7 +138,7 @@ struct Shape {
   int64_t qtmax = 1;   // max partial weights per sample
   int64_t kpmax = 64;  // max padded K of the 16-bit left vectors
   int64_t bmax = 1;    // max packed site-tensor elements
-  int64_t csmax = 1;   // max d_k * (padded chi_{k+1}): column scales (MPS_FP16F8)
+  int64_t csmax = 1;   // max d_k * (padded chi_{k+1}): column scales (MPS_FP16F8, MPS_FP16F6)
 };
 
 struct ChainBufs {
@@ -248,7 +248,7 @@ struct Step {
   int tn_tot[2] = {0, 0};
   size_t ctab[2] = {0, 0}, tntab[2] = {0, 0};
   int blk_total = 0;  // packing blocks over all problems of the step
-  int cm_total = 0;   // column-scale blocks (MPS_FP16F8)
+  int cm_total = 0;   // column-scale blocks (MPS_FP16F8, MPS_FP16F6)
   int meas_rpw = 64;  // samples per wave in the measurement (set by the largest chi_r)
   size_t pack = 0, blk_start = 0, measure = 0, cm_start = 0;  // offsets in the table blob
   double flops_per_row = 0, meas_bytes_per_row = 0;

@@ -131,12 +131,12 @@ struct ContractProb {
 struct PackProb {
   const float2* A;   // [K][d][chi_r] complex site tensor
   void* Bh;          // [d*CP*2][Kp] 16-bit real embedding, K contiguous
-  void* Bl;          // low parts (split forms; kFp16F8: the FP8 pair plane)
+  void* Bl;          // low parts (split forms; kFp16F8: the FP8 pair plane; kFp16F6: the FP6 records)
   int K, d, chi_r, CP, Kp;
-  float* colscale;   // kFp16F8: [d*CP] power-of-two scale s_c per complex column
-  float* colpart;    // kFp16F8: [colmax_blocks(K)][d*CP] column maxima of row blocks
+  float* colscale;   // kFp16F8, kFp16F6: [d*CP] power-of-two scale s_c per complex column
+  float* colpart;    // kFp16F8, kFp16F6: [colmax_blocks(K)][d*CP] column maxima of row blocks
 };
-// kFp16F8 column maxima: the K rows of a site tensor in at most 16 blocks.
+// kFp16F8 / kFp16F6 column maxima: the K rows of a site tensor in at most 16 blocks.
 __host__ __device__ inline int colmax_blocks(int K) { return K < 64 * 16 ? (K + 63) / 64 : 16; }
 
 struct ContractLpProb {
@@ -147,7 +147,7 @@ struct ContractLpProb {
   float2* W;         // [rows][d*chi_r] complex FP32
   float* qpart;      // [rows][d*T], T = CP / kPartCols
   int Kp, d, chi_r, CP;
-  const float* colscale;  // kFp16F8: [d*CP] column scales s_c
+  const float* colscale;  // kFp16F8, kFp16F6: [d*CP] column scales s_c
 };
 
 struct MeasureProb {
@@ -224,7 +224,7 @@ hipError_t launch_contract_f32(int tile, const ContractProb* probs, const int* t
                                const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s);
 hipError_t launch_pack_lp(int form, const PackProb* probs, const int* blk_start, int nprob, int blk_total,
                           hipStream_t s);
-// kFp16F8: column maxima of the problems' site tensors per row block (before
+// kFp16F8, kFp16F6: column maxima of the problems' site tensors per row block (before
 // launch_pack_lp, which reduces them to the column scales); one workgroup per
 // (row block, branch, 64 complex columns), cm_start[p] = first workgroup of
 // problem p (nprob + 1 entries).
