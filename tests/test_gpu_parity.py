@@ -200,6 +200,26 @@ def test_flagged_samples(mpsmod, form):
     assert np.all(np.isneginf(g["logp"]))
 
 
+@pytest.mark.parametrize("bad", ["nan", "inf"])
+@pytest.mark.parametrize("form", FORMS)
+def test_non_finite_site_entry_flags_every_sample(mpsmod, form, bad):
+    """One NaN or infinite entry in a site tensor reaches every sample's W
+    (0 * NaN and 0 * inf are NaN), so every sample is flagged at that site:
+    MPS_ENUMERIC, outcome -1 from there on, logp -inf; the sites before it
+    are sampled as usual."""
+    _say(f"non-finite site entry ({bad}) at site 3 {form}")
+    t = _chain(14, 8, 3, 9)
+    ref = _run(mpsmod, t, 400, seed=1, precision=form)
+    t[3] = t[3].copy()
+    t[3][1, 0, 2] = np.complex64(complex(float(bad), 0.0))
+    g = _run(mpsmod, t, 400, seed=1, precision=form)
+    assert g["status"] == mpsmod.MPS_ENUMERIC
+    assert g["stats"].flagged == 400
+    assert np.all(g["outcomes"][:, 3:] == -1)
+    assert np.array_equal(g["outcomes"][:, :3], ref["outcomes"][:, :3])
+    assert np.all(np.isneginf(g["logp"]))
+
+
 def test_empty_and_memory_cap(mpsmod):
     _say("N=0 and max_device_bytes forcing small chunks")
     t = _chain(15, 6, 4, 16)
