@@ -8,8 +8,8 @@ the benchmark times, on sampled rows that the oracle computes one by one:
   conditional probability up to there;
 * uneven chain M = 2048, d_k in {2..6}, chi <= 4096 (bf16 hi+lo, one
   8192-sample chunk) -- first 10 sites;
-* the batched 256-chain ensemble (FP32, N = 8192 each) -- whole chains, for
-  a few chains and rows.
+* the batched 256-chain ensemble (FP32, and fp16f6 with per-shape tuned
+  tiles; N = 8192 each) -- whole chains, for a few chains and rows.
 
 The large-bond sites are the structured right-canonical sites of the input
 generator: bond blocks visited as a hidden Markov chain, with per-column
@@ -129,10 +129,13 @@ def test_uneven_chain_prefix_parity(form):
     print("prefix call", rep, flush=True)
 
 
-def test_full_ensemble_sampled_parity():
+@pytest.mark.parametrize("form", ["fp32", "fp16f6"])
+def test_full_ensemble_sampled_parity(form):
+    """The batched ensemble in FP32 (its configured form, bar 1e-5) and in the
+    headline low-precision form with per-shape tuned tiles (bar 1e-3)."""
     from paper_2512_20064_amd import mps
     from tests.parity_util import compare, upload
-    print("[gpu-case] 256-chain ensemble, N=8192, fp32", flush=True)
+    print(f"[gpu-case] 256-chain ensemble, N=8192, {form}", flush=True)
     specs = synth.ensemble_specs(seed=2, B=256)
     chains = []
     for b, (Mb, db, cb) in enumerate(specs):
@@ -140,8 +143,13 @@ def test_full_ensemble_sampled_parity():
         chains.append(synth.to_c64(synth.random_mps(7, dl, synth.ramp_bonds(dl, cb), mps_id=b, pool=4)))
     dev = [upload(c) for c in chains]
     N, seed = 8192, 77
-    s = mps.Sampler(0, n_chunk=8192)
-    outs = s.sample_batch(dev, N, seed)
+    s = mps.Sampler(0, n_chunk=8192, precision=form)
+    if form != "fp32":
+        prep = mps.prepare_batch(dev)
+        s.autotune_tiles(prep, N)
+        outs = s.sample_batch(prep, N, seed)
+    else:
+        outs = s.sample_batch(dev, N, seed)
     torch.cuda.synchronize()
     assert s.status == 0
     s.close()
@@ -149,5 +157,5 @@ def test_full_ensemble_sampled_parity():
     rows = np.concatenate([np.arange(6), np.array([4096, N - 1])])
     for b in sorted({0, 128, 255, biggest}):
         gpu = {"outcomes": outs[b][0].cpu().numpy(), "logp": outs[b][1].cpu().numpy()}
-        rep = compare(chains[b], seed, gpu, rows=rows, mps_id=b)
+        rep = compare(chains[b], seed, gpu, rows=rows, mps_id=b, eps=1e-5 if form == "fp32" else 1e-3)
         print(b, specs[b], rep, flush=True)
