@@ -556,21 +556,28 @@ __global__ __launch_bounds__(256) void pack_f16f8_kernel(const PackProb* probs, 
       // a record that small flushes to zero)
       const int ke = max(e2m3_scale_exp(m), -108);
       const float inv2 = ldexpf(1.f, -ke);
-      unsigned cl[8], chh[8];
+      uint64_t l8 = 0, h8 = 0;  // this thread's 8 low-part and 8 high-part codes, 6 bits each
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        cl[e] = e2m3_code(lo[e] * inv2);
-        chh[e] = e2m3_code(hf[e] * inv2);
+        l8 |= (uint64_t)e2m3_code(lo[e] * inv2) << (6 * e);
+        h8 |= (uint64_t)e2m3_code(hf[e] * inv2) << (6 * e);
       }
-      // site record: codes 0..15 the low part, 16..31 the high part; this
-      // thread's 8 K values are codes (k & 8) .. +7 of each half
-      unsigned char* rec = B8 + pair_off(orow, k & ~15, a.Kp);
+      // Site record: codes 0..15 the low part, 16..31 the high part, K 0..7
+      // of the slice from the thread with (k & 8) == 0, K 8..15 from its
+      // neighbour.  Both threads assemble the 192 code bits and each stores
+      // one 16-byte half: [l0 | l1 | h0 | h1] (48 bits each), then byte 24
+      // the scale (the corrections' common 2^-19 rides on the site's scale)
+      // and zeros.
+      const uint64_t pl = __shfl_xor(l8, 1), ph = __shfl_xor(h8, 1);
       const int q = (k & 8) ? 1 : 0;
-      e2m3_store8(rec + 6 * q, cl);
-      e2m3_store8(rec + 12 + 6 * q, chh);
-      // byte 24: the scale (the corrections' common 2^-19 rides on the site's
-      // scale); bytes 25..31 zero
-      *reinterpret_cast<uint32_t*>(rec + 24 + 4 * q) = q == 0 ? (uint32_t)(127 + ke - 19) : 0u;
+      const uint64_t l0 = q ? pl : l8, l1 = q ? l8 : pl, h0 = q ? ph : h8, h1 = q ? h8 : ph;
+      unsigned char* rec = B8 + pair_off(orow, k & ~15, a.Kp);
+      if (q == 0)
+        *reinterpret_cast<uint4*>(rec) = make_uint4((uint32_t)l0, (uint32_t)(l0 >> 32) | (uint32_t)(l1 << 16),
+                                                    (uint32_t)(l1 >> 16), (uint32_t)h0);
+      else
+        *reinterpret_cast<uint4*>(rec + 16) = make_uint4((uint32_t)(h0 >> 32) | (uint32_t)(h1 << 16),
+                                                         (uint32_t)(h1 >> 16), (uint32_t)(127 + ke - 19), 0u);
     }
   }
 }

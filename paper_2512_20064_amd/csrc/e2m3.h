@@ -39,18 +39,6 @@ __host__ __device__ inline int e2m3_scale_exp(float amax) {
   return k < -126 ? -126 : (k > 127 ? 127 : k);
 }
 
-// Eight codes as 48 bits (code j at bits 6j .. 6j+5), written as three
-// 16-bit words (the 6-byte run starts at an even byte).
-__device__ inline void e2m3_store8(unsigned char* dst, const unsigned (&c)[8]) {
-  uint64_t b = 0;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) b |= (uint64_t)(c[j] & 63u) << (6 * j);
-  uint16_t* d = reinterpret_cast<uint16_t*>(dst);
-  d[0] = (uint16_t)b;
-  d[1] = (uint16_t)(b >> 16);
-  d[2] = (uint16_t)(b >> 32);
-}
-
 // A whole 32-byte record: codes 0..31 in bytes 0..23, the E8M0 scale code in
 // byte 24, zeros after.
 __device__ inline void e2m3_store_record(unsigned char* dst, const unsigned (&c)[32], unsigned scale_code) {
