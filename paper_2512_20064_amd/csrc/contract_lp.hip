@@ -772,9 +772,12 @@ __device__ inline void contract_f16f8_body(const ContractLpProb* probs, const in
   // mma16(h) cover the reads of h only; the last three pairs take the
   // general step below.
   int m = 0;
+  // The FP8/FP6 operands of the next pair are read right after the barrier,
+  // before mma16(h) (their registers are free once mma8(f) has issued), so
+  // that they have the whole of mma16(h) and mma16(e') to arrive; the
+  // reads of h may mix with the MFMAs of e.
   for (; m + 3 < npair; ++m) {
     mma16(e);
-    __builtin_amdgcn_sched_barrier(0);
     read16(2 * m + 1, h);
     mma8(f);
     __builtin_amdgcn_sched_barrier(0);
@@ -784,9 +787,9 @@ __device__ inline void contract_f16f8_body(const ContractLpProb* probs, const in
     issue(issued++);
     __builtin_amdgcn_sched_barrier(0);
     read16(2 * m + 2, e);
+    read8(m + 1, f);
     mma16(h);
     __builtin_amdgcn_sched_barrier(0);
-    read8(m + 1, f);
   }
   for (; m < npair; ++m) {
     mma16(e);
