@@ -24,7 +24,8 @@
 // does the same job, keeps every element of l' within [-1, 1], and the scale
 // cancels in q_i / S.  The log-norm of the path is tracked in logp.
 //
-// Without displacement (measure_rows_kernel) a workgroup measures 64 rows:
+// Without displacement (measure_rows_kernel) a workgroup measures 64 rows
+// (16 in launches too small to fill the GPU with 64-row workgroups):
 // one lane per row makes the decision (the scalar FP64 and 64-bit integer
 // work, once per row), then groups of min(meas_lanes(chi_r), 16) lanes (down
 // to one lane for chi_r <= 4) gather the chosen branches.  With displacement
@@ -522,23 +523,24 @@ __global__ __launch_bounds__(256) void measure_kernel(const MeasureProb* probs, 
 //      that several rows' loads are in flight together.
 // The arithmetic, its order and every stored value are those of the
 // one-group-per-row form used with displacement above.
-constexpr int kRowsPerBlock = 64;
-static_assert(kRowsPerBlock <= 64, "one lane of wave 0 per row in the decision phase");
-
-template <int OUT>
+// RPB rows per workgroup: 64, or 16 when a launch of 64-row workgroups would
+// leave CUs idle (few rows per chunk at a large bond: 8192 rows make 128
+// workgroups of 64 rows for 256 CUs).  A row's results do not depend on RPB.
+template <int OUT, int RPB>
 __global__ __launch_bounds__(256) void measure_rows_kernel(const MeasureProb* probs, const ChunkArgs* chp,
                                                            uint64_t seed, int* nflag) {
-  __shared__ int s_sh[kRowsPerBlock];       // chosen branch, -1 if the row is flagged or past the chunk
-  __shared__ float scale_sh[kRowsPerBlock];  // 1 / sqrt(q_s)
+  static_assert(RPB <= 64 && 64 % RPB == 0, "one lane of wave 0 per row in the decision phase");
+  __shared__ int s_sh[RPB];       // chosen branch, -1 if the row is flagged or past the chunk
+  __shared__ float scale_sh[RPB];  // 1 / sqrt(q_s)
   const ChunkArgs ch = *chp;
   const MeasureProb a = probs[blockIdx.y];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  const int row0 = blockIdx.x * kRowsPerBlock;
+  const int row0 = blockIdx.x * RPB;
   if (row0 >= ch.rows) return;  // the whole workgroup
   const int d = a.d, T = a.T;
 
-  if (wv == 0 && lane < kRowsPerBlock) {
+  if (wv == 0 && lane < RPB) {
     const int row = row0 + lane;
     int sv = -1;
     float scale = 0.f;
@@ -613,14 +615,14 @@ __global__ __launch_bounds__(256) void measure_rows_kernel(const MeasureProb* pr
   const int g = lane / W, sl = lane & (W - 1);
   const int nq = (a.chi_r + PC - 1) / PC;  // pieces per row
   const int iters = (nq + W - 1) / W;
-  const int nsteps = (kRowsPerBlock + 4 * G - 1) / (4 * G);
+  const int nsteps = (RPB + 4 * G - 1) / (4 * G);
   const bool even = (a.chi_r & 1) == 0;  // a piece is then 16-byte aligned
 #pragma unroll 4
   for (int t = 0; t < nsteps * iters; ++t) {
     const int k = t / iters, it = t - k * iters;
     const int rloc = (k * 4 + wv) * G + g;
     const int qp = sl + it * W;
-    if (rloc >= kRowsPerBlock || qp >= nq) continue;
+    if (rloc >= RPB || qp >= nq) continue;
     const int sv = s_sh[rloc];
     if (sv < 0) continue;
     const int row = row0 + rloc;
@@ -654,7 +656,7 @@ __global__ __launch_bounds__(256) void measure_rows_kernel(const MeasureProb* pr
   // K padding of the 16-bit operand rows past the written pieces
   for (int k = 0; k < nsteps; ++k) {
     const int rloc = (k * 4 + wv) * G + g;
-    if (rloc < kRowsPerBlock && s_sh[rloc] >= 0) LWriter<OUT>(a, row0 + rloc).pad_from(2 * PC * nq, sl, W);
+    if (rloc < RPB && s_sh[rloc] >= 0) LWriter<OUT>(a, row0 + rloc).pad_from(2 * PC * nq, sl, W);
   }
 }
 
@@ -777,15 +779,21 @@ hipError_t launch_zero_int(int* p, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// 64-row workgroups from two per CU on (512 of them); below that, 16-row ones.
+constexpr long long kMeasureFullGrid = 512;
+
 template <int OUT>
 void launch_measure_t(bool displaced, int grid_rows, int nprob, const MeasureProb* probs, const ChunkArgs* ch,
                       uint64_t seed, int* nflag, hipStream_t s) {
   if (displaced)  // one wave per row
     hipLaunchKernelGGL((measure_kernel<OUT, true>), dim3((grid_rows + 3) / 4, nprob), dim3(256), 0, s, probs, ch,
                        seed, nflag);
+  else if ((long long)((grid_rows + 63) / 64) * nprob >= kMeasureFullGrid)
+    hipLaunchKernelGGL((measure_rows_kernel<OUT, 64>), dim3((grid_rows + 63) / 64, nprob), dim3(256), 0, s, probs,
+                       ch, seed, nflag);
   else
-    hipLaunchKernelGGL((measure_rows_kernel<OUT>), dim3((grid_rows + kRowsPerBlock - 1) / kRowsPerBlock, nprob),
-                       dim3(256), 0, s, probs, ch, seed, nflag);
+    hipLaunchKernelGGL((measure_rows_kernel<OUT, 16>), dim3((grid_rows + 15) / 16, nprob), dim3(256), 0, s, probs,
+                       ch, seed, nflag);
 }
 
 hipError_t launch_measure(int form, const MeasureProb* probs, int nprob, const ChunkArgs* ch, int grid_rows,

@@ -188,6 +188,20 @@ def test_chunking_and_offset_bit_exact(mpsmod, form):
 
 
 @pytest.mark.parametrize("form", FORMS)
+def test_measurement_workgroup_size_bit_exact(mpsmod, form):
+    """A 40000-row chunk is measured by 64-row workgroups (625 of them), an
+    8192-row chunk by 16-row ones (128 workgroups of 64 rows would leave
+    CUs idle): the same samples come out bit-identical either way."""
+    _say(f"measurement workgroup size M=6 d=4 chi=64 N=40000 {form}")
+    t = _chain(17, 6, 4, 64)
+    one = _run(mpsmod, t, 40000, seed=5, n_chunk=40000, precision=form)
+    small = _run(mpsmod, t, 40000, seed=5, n_chunk=8192, precision=form)
+    assert one["status"] == 0 and small["status"] == 0
+    assert np.array_equal(one["outcomes"], small["outcomes"])
+    assert np.array_equal(one["logp"], small["logp"])
+
+
+@pytest.mark.parametrize("form", FORMS)
 def test_flagged_samples(mpsmod, form):
     """A zero site tensor stops every sample: MPS_ENUMERIC, -1 outcomes, -inf logp."""
     _say(f"flagged samples: zero tensor at site 3 {form}")
