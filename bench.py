@@ -231,17 +231,29 @@ def cpu_baseline(t128, seed, n_samples, n_sites, n_samples_1t):
             "host": hi}
 
 
-def roofline_of(form, c_fl, c_n, c_ms, dt, m_ms, p_ms, chunk, chi, products=None):
+HBM_PEAK_GBS = 8000.0
+
+
+def roofline_of(form, c_fl, c_n, c_ms, dt, m_ms, p_ms, chunk, chi, products=None, m_bytes=None, m_n=None):
     """Roofline of the contraction kernel: algorithmic flops (8 d chi_l chi_r
     per site-sample, the complex contraction itself) per launch over the
     event-timed average launch, against the dense MFMA peak of the operand
     type.  A split form issues mfma_per_alg MFMA products per complex
     product; its issued MFMA rate is reported beside (mfma_issued), not as
-    the achieved figure."""
+    the achieved figure.  With m_bytes and m_n (the library's algorithmic
+    bytes of the measurement launches and their count) the HBM-bound
+    measurement kernel's rate against the HBM peak is reported beside."""
     f = FORMS[form]
     products = products or f["mfma_per_alg"]
     alg = (c_fl / c_n) / (c_ms / c_n * 1e-3) / 1e12
     issued = alg * products
+    extra = {}
+    if m_bytes and m_n and m_ms > 0:
+        gbs = m_bytes / (m_ms * 1e-3) / 1e9
+        extra["measure"] = {"bound": "hbm", "kernel": "measure_rows_kernel", "achieved": round(gbs, 1),
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                            "bytes_per_launch": round(m_bytes / m_n), "avg_launch_ms": round(m_ms / m_n, 4),
+                            "launches": m_n}
     return {
         "bound": "mfma", "achieved": round(alg, 2), "peak": f["peak"], "unit": "TFLOP/s",
         "frac": round(alg / f["peak"], 4), "traffic": traffic_for(form, chunk, chi),
@@ -252,6 +264,7 @@ def roofline_of(form, c_fl, c_n, c_ms, dt, m_ms, p_ms, chunk, chi, products=None
         "avg_launch_ms": round(c_ms / c_n, 4), "launches": c_n,
         "time_share": {"contract": round(c_ms * 1e-3 / dt, 4), "measure": round(m_ms * 1e-3 / dt, 4),
                        "pack": round(p_ms * 1e-3 / dt, 4)},
+        **extra,
     }
 
 
@@ -335,14 +348,16 @@ def run_chain_bench(args):
             torch.cuda.synchronize()
             log(f"{form} warmup step {w} done")
         torch.cuda.synchronize()
-        c_ms = m_ms = p_ms = c_fl = f_ms = f_fl = 0.0
-        c_n = f_n = 0
+        c_ms = m_ms = p_ms = c_fl = f_ms = f_fl = m_b = 0.0
+        c_n = f_n = m_n = 0
         t0 = time.perf_counter()
         for s_ in range(steps):
             one_step()
             st = sampler.stats
             c_ms += st.contract_ms
             m_ms += st.measure_ms
+            m_b += st.measure_bytes
+            m_n += st.measure_launches
             p_ms += st.pack_ms
             c_fl += st.contract_flops
             c_n += st.contract_launches
@@ -356,7 +371,8 @@ def run_chain_bench(args):
         out = {"value": args.chunk * M * steps / dt, "ms_per_step": dt / steps * 1e3, "dt": dt,
                "alg_tflops": (c_fl + f_fl) / dt / 1e12}
         if not args.no_profile and c_ms > 0:
-            out["roofline"] = roofline_of(form, c_fl, c_n, c_ms, dt, m_ms, p_ms, args.chunk, args.chi)
+            out["roofline"] = roofline_of(form, c_fl, c_n, c_ms, dt, m_ms, p_ms, args.chunk, args.chi,
+                                          m_bytes=m_b, m_n=m_n)
         elif not args.no_profile and f_ms > 0:
             out["roofline"] = roofline_small(f_fl, f_n, f_ms, dt)
         return out
@@ -482,7 +498,8 @@ def run_stream_bench(args):
         # fp16 split form skips the product with the (zero) low parts
         "roofline": (roofline_of(args.precision, st.contract_flops, st.contract_launches, st.contract_ms,
                                  dt, st.measure_ms, st.pack_ms, args.chunk, args.chi,
-                                 products=2 if (args.precision == "fp16x3" and kind in ("cf16", "cf8")) else None)
+                                 products=2 if (args.precision == "fp16x3" and kind in ("cf16", "cf8")) else None,
+                                 m_bytes=st.measure_bytes, m_n=st.measure_launches)
                      if st.contract_ms > 0 else None),
         "cpu_baseline": None,
     }

@@ -30,6 +30,16 @@ def test_roofline_reports_algorithmic_flops_against_the_operand_peak():
     assert two["kernel"] == "contract_lp_kernel<f16,2>" and two["mfma_issued"]["tflops"] == pytest.approx(2000.0)
 
 
+def test_roofline_reports_the_measurement_kernel_against_the_hbm_peak():
+    # 4 measurement launches moving 1 GB each in 1 ms in all: 4 TB/s of the 8 TB/s peak
+    r = bench.roofline_of("fp16f6", 1e15, 10, 1000.0, 2.0, 1.0, 1.0, 65536, 1024, m_bytes=4e9, m_n=4)
+    m = r["measure"]
+    assert m["bound"] == "hbm" and m["unit"] == "GB/s" and m["peak"] == 8000.0
+    assert m["achieved"] == pytest.approx(4000.0) and m["frac"] == pytest.approx(0.5)
+    assert m["bytes_per_launch"] == 1000000000 and m["avg_launch_ms"] == pytest.approx(0.25) and m["launches"] == 4
+    assert "measure" not in bench.roofline_of("fp16f6", 1e15, 10, 1000.0, 2.0, 1.0, 1.0, 65536, 1024)
+
+
 def test_traffic_record_is_ignored_for_another_kernel_version(tmp_path, monkeypatch):
     rec = {"kernel_sha": bench.kernel_hash("bf16x3"), "chunk": 65536, "chi": 1024, "bytes_per_launch": 123}
     (tmp_path / "profiles").mkdir()
