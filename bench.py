@@ -29,6 +29,10 @@ Other workloads (one JSON line each, not the headline):
                       with 128 x 128 block scales), copied on a side stream
                       while the previous site computes: per-site time, H2D
                       GB/s and the copy/compute overlap.
+  --displace SIGMA    (resident, uneven, small) per-sample displacement of
+                      the physical index (the GBS variant, Eq. 7), complex
+                      Gaussian of scale SIGMA; the oracle baseline is
+                      displaced the same way.
 """
 from __future__ import annotations
 
@@ -187,41 +191,46 @@ def host_info():
     return info
 
 
-def _oracle_rate(tensors, seed, n_samples, threads=None):
+def _oracle_rate(tensors, seed, n_samples, threads=None, displace=None):
     """site-samples/s of the FP64 oracle on samples 0 .. n_samples-1 of a chain
     (window with an open right end), with the BLAS thread count limited to
-    `threads` (None: as configured)."""
+    `threads` (None: as configured); displace: complex [n_samples, sites]
+    per-sample displacements, or None."""
     import oracle
     from threadpoolctl import threadpool_limits, threadpool_info
     with threadpool_limits(limits=threads, user_api="blas"):
         used = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("user_api") == "blas"] or [1])
         t0 = time.perf_counter()
-        oracle.sample(tensors, seed=seed, N=n_samples)
+        oracle.sample(tensors, seed=seed, N=n_samples, displace=displace)
         dt = time.perf_counter() - t0
     return n_samples * len(tensors) / dt, dt, int(used)
 
 
-def cpu_baseline(t128, seed, n_samples, n_sites, n_samples_1t):
+def cpu_baseline(t128, seed, n_samples, n_sites, n_samples_1t, mu=None):
     """The FP64 oracle as it stands, timed on the host cores.
 
     value: all BLAS threads, samples 0 .. n_samples-1 (global indices) over
     the first n_sites sites of the benchmarked chain (the 5 ramp sites and
     the plateau after them).  Beside it: the same sites single-threaded on
     n_samples_1t samples, and the small parity chain (M = 32, d = 4,
-    chi = 32, N = 4096) in full at both thread counts."""
+    chi = 32, N = 4096) in full at both thread counts.  mu: the benchmark's
+    per-sample displacements (complex [samples, M]) when it runs displaced;
+    the chain legs then take the same displacements."""
     import numpy  # noqa: F401  (loads the BLAS that threadpoolctl reports)
     from paper_2512_20064_amd import synth
     hi = host_info()
     window = t128[:n_sites]
-    v, dt, used = _oracle_rate(window, seed, n_samples)
-    v1, dt1, _ = _oracle_rate(window, seed, n_samples_1t, threads=1)
+    mu_w = None if mu is None else mu[:, :n_sites]
+    v, dt, used = _oracle_rate(window, seed, n_samples, displace=None if mu_w is None else mu_w[:n_samples])
+    v1, dt1, _ = _oracle_rate(window, seed, n_samples_1t, threads=1,
+                              displace=None if mu_w is None else mu_w[:n_samples_1t])
     small = synth.small_chain(1, M=32, d=4, chi_max=32)[0]
     vs, dts, _ = _oracle_rate(small, 1001, 4096)
     vs1, dts1, _ = _oracle_rate(small, 1001, 4096, threads=1)
     return {"value": v, "unit": "site-samples/s", "cores": used, "kind": "oracle",
             "sample": (f"global samples 0..{n_samples - 1} x first {n_sites} sites of the benchmarked chain "
-                       f"(ramp 1,4,16,64,256 then chi=1024 plateau), numpy FP64 with {used} BLAS threads, "
-                       f"{dt:.1f}s"),
+                       f"(ramp 1,4,16,64,256 then chi=1024 plateau){'' if mu is None else ', displaced'}, "
+                       f"numpy FP64 with {used} BLAS threads, {dt:.1f}s"),
             "single_thread": {"value": v1, "unit": "site-samples/s", "cores": 1,
                               "sample": f"global samples 0..{n_samples_1t - 1} x the same {n_sites} sites, "
                                         f"{dt1:.1f}s"},
@@ -234,7 +243,8 @@ def cpu_baseline(t128, seed, n_samples, n_sites, n_samples_1t):
 HBM_PEAK_GBS = 8000.0
 
 
-def roofline_of(form, c_fl, c_n, c_ms, dt, m_ms, p_ms, chunk, chi, products=None, m_bytes=None, m_n=None):
+def roofline_of(form, c_fl, c_n, c_ms, dt, m_ms, p_ms, chunk, chi, products=None, m_bytes=None, m_n=None,
+                m_kernel="measure_rows_kernel"):
     """Roofline of the contraction kernel: algorithmic flops (8 d chi_l chi_r
     per site-sample, the complex contraction itself) per launch over the
     event-timed average launch, against the dense MFMA peak of the operand
@@ -250,7 +260,7 @@ def roofline_of(form, c_fl, c_n, c_ms, dt, m_ms, p_ms, chunk, chi, products=None
     extra = {}
     if m_bytes and m_n and m_ms > 0:
         gbs = m_bytes / (m_ms * 1e-3) / 1e9
-        extra["measure"] = {"bound": "hbm", "kernel": "measure_rows_kernel", "achieved": round(gbs, 1),
+        extra["measure"] = {"bound": "hbm", "kernel": m_kernel, "achieved": round(gbs, 1),
                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                             "bytes_per_launch": round(m_bytes / m_n), "avg_launch_ms": round(m_ms / m_n, 4),
                             "launches": m_n}
@@ -311,6 +321,17 @@ def run_chain_bench(args):
 
     tuned = {}
     tiles = {}
+    mu = None
+    if args.displace > 0:
+        # per-sample displacements of the GBS variant (complex Gaussian, each
+        # component of standard deviation sigma / sqrt(2)), one row per
+        # sample of a step, drawn once outside the timed region and reused
+        # for every step
+        g = torch.Generator(device="cuda")
+        g.manual_seed(77)
+        mu = (torch.randn(args.chunk, M, 2, generator=g, device="cuda") * (args.displace / 2 ** 0.5))
+        mu = torch.view_as_complex(mu).contiguous()
+        log(f"displacements: sigma {args.displace}, {mu.numel() * 8 / 2**20:.0f} MiB")
 
     def run_form(form, steps, warmup):
         sampler = mps.Sampler(0, n_chunk=args.chunk, profile=not args.no_profile, precision=form,
@@ -339,7 +360,7 @@ def run_chain_bench(args):
 
         def one_step():
             r = sampler.sample(dev, args.chunk, seed, n_offset=step[0] * args.chunk, want_logp=True,
-                               stream=gstream)
+                               stream=gstream, displace=mu)
             step[0] += 1
             return r
 
@@ -372,7 +393,8 @@ def run_chain_bench(args):
                "alg_tflops": (c_fl + f_fl) / dt / 1e12}
         if not args.no_profile and c_ms > 0:
             out["roofline"] = roofline_of(form, c_fl, c_n, c_ms, dt, m_ms, p_ms, args.chunk, args.chi,
-                                          m_bytes=m_b, m_n=m_n)
+                                          m_bytes=m_b, m_n=m_n,
+                                          m_kernel="measure_disp_kernel" if mu is not None else "measure_rows_kernel")
         elif not args.no_profile and f_ms > 0:
             out["roofline"] = roofline_small(f_fl, f_n, f_ms, dt)
         return out
@@ -391,7 +413,12 @@ def run_chain_bench(args):
     cpu = None
     if not args.no_cpu_baseline and t128 is not None:
         log("timing the FP64 oracle on the host")
-        cpu = cpu_baseline(t128, seed, args.cpu_samples, min(args.cpu_sites, M), args.cpu_samples_1t)
+        mu_host = None
+        if mu is not None:
+            rows = min(max(args.cpu_samples, args.cpu_samples_1t), args.chunk)
+            mu_host = mu[:rows].cpu().numpy().astype(np.complex128)
+        cpu = cpu_baseline(t128, seed, min(args.cpu_samples, args.chunk), min(args.cpu_sites, M),
+                           min(args.cpu_samples_1t, args.chunk), mu=mu_host)
 
     metric = METRIC if args.workload == "resident" else f"site-samples/s, {args.workload} chain"
     rec = {
@@ -401,7 +428,8 @@ def run_chain_bench(args):
         "data": "synthetic",
         "config": {"workload": wname, "sites": M, "d": (4 if args.workload != "uneven" else "2..6"),
                    "chi": int(max(chi)), "samples_per_step": args.chunk,
-                   "precision": args.precision, "tensor_bytes": distinct_bytes(dev)},
+                   "precision": args.precision, "tensor_bytes": distinct_bytes(dev),
+                   "displace_sigma": args.displace or None},
         "roofline": roof, "cpu_baseline": cpu,
     }
     if tuned:
@@ -618,6 +646,8 @@ def main():
     ap.add_argument("--tile-tune", type=int, default=1, help="pick the tile shape per site shape first")
     ap.add_argument("--beside", default=None, help="comma-separated forms also timed ('' for none)")
     ap.add_argument("--beside-steps", type=int, default=1)
+    ap.add_argument("--displace", type=float, default=0.0, metavar="SIGMA",
+                    help="chain workloads: per-sample complex Gaussian displacements of scale SIGMA (GBS)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=4096, help="oracle samples, all BLAS threads")
     ap.add_argument("--cpu-samples-1t", type=int, default=256, help="oracle samples, one BLAS thread")

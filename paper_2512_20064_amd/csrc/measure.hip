@@ -29,8 +29,8 @@
 // one lane per row makes the decision (the scalar FP64 and 64-bit integer
 // work, once per row), then groups of min(meas_lanes(chi_r), 16) lanes (down
 // to one lane for chi_r <= 4) gather the chosen branches.  With displacement
-// (measure_kernel) one wave measures one row: it builds that row's D in its
-// LDS and forms the weights from W' directly.
+// (measure_disp_kernel) one wave measures one row: it builds that row's D in
+// its LDS and forms the weights from W' directly.
 
 #include "e2m3.h"
 #include "philox.h"
@@ -317,74 +317,77 @@ __device__ inline float2 displacement_entry(double mr, double mi, int i, int j) 
   return make_float2((float)(g * sr), (float)(g * si));
 }
 
-// DISP: the launch's problems carry a displacement (mu != NULL).  A separate
-// instantiation keeps the displaced path's registers out of the plain one.
-template <int OUT, bool DISP>
-__global__ __launch_bounds__(256) void measure_kernel(const MeasureProb* probs, const ChunkArgs* chp, uint64_t seed,
-                                                      int* nflag) {
-  __shared__ float2 Dsh[4][DMAX * DMAX];  // displacement operator of each wave's sample
+// Measurement with per-sample displacement (Eq. 7), one wave per row.  The
+// wave builds D(mu) of its sample in LDS, forms the branch weights of
+// W' = D(mu) W over the physical index (each lane sums |W'_i(r)|^2 over its
+// columns r = lane + 64 t in FP32, the lanes' sums are added in FP64 by a
+// fixed butterfly), draws, and gathers the chosen branch W'_s.  DM >= d (4,
+// 8 or 16) sizes the per-lane arrays so that the loads of a step are all
+// issued before its arithmetic: UNR columns per lane at a time in the
+// weights pass, and in the gather a piece of PC consecutive complex of every
+// branch (16-byte loads when chi_r is even).
+template <int OUT, int DM>
+__global__ __launch_bounds__(256) void measure_disp_kernel(const MeasureProb* probs, const ChunkArgs* chp,
+                                                           uint64_t seed, int* nflag) {
+  static_assert(DM <= DMAX, "physical dimension");
+  constexpr int UNR = DM <= 4 ? 4 : (DM <= 8 ? 2 : 1);
+  constexpr int PC = OUT == kOutF16F6 ? 8 : 4;  // the fp16f6 records take whole 16-K slices
+  __shared__ float2 Dsh[4][DM * DM];            // displacement operator of each wave's sample
   const ChunkArgs ch = *chp;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const MeasureProb a = probs[blockIdx.y];
-  const int W = DISP ? 64 : meas_lanes(a.chi_r);  // lanes per sample
-  const int sl = lane & (W - 1);                  // lane within the sample's group
-  const int row = (blockIdx.x * 4 + wv) * (64 / W) + lane / W;
+  const int row = blockIdx.x * 4 + wv;
   if (row >= ch.rows) return;
   const int64_t crow = ch.c0 + row;  // row within the call
   double* const logp = a.logp + (a.logp_in_call ? crow : row);
-  const int d = a.d, T = a.T;
-  const bool disp = DISP && a.mu != nullptr;
-  const float2* Wrow = a.W + (size_t)row * d * a.chi_r;
+  const int d = a.d, n = a.chi_r;
+  const float2* Wrow = a.W + (size_t)row * d * n;
 
-  double q[DMAX];
-  if (!disp) {
-    // branch weights from the contraction's partial sums
-    const float* qp = a.qpart + (size_t)row * (d * T);
+  const float2 mu = a.mu[(size_t)crow * a.M + a.site];
+  for (int t = lane; t < d * d; t += 64) Dsh[wv][t] = displacement_entry(mu.x, mu.y, t / d, t % d);
+  __builtin_amdgcn_wave_barrier();
+  const float2* D = Dsh[wv];
+
+  // branch weights of W'
+  float qa[DM];
 #pragma unroll
-    for (int i = 0; i < DMAX; ++i) {
-      double qi = 0.0;
-      if (i < d)
-        for (int t = 0; t < T; ++t) qi += (double)qp[i * T + t];
-      q[i] = qi;
-    }
-  } else {
-    // W' = D(mu) W over the physical index; weights of W' summed per lane in
-    // FP32 over its columns r, then across lanes in FP64 (fixed butterfly).
-    const float2 m = a.mu[(size_t)crow * a.M + a.site];
-    for (int t = lane; t < d * d; t += 64) Dsh[wv][t] = displacement_entry(m.x, m.y, t / d, t % d);
-    __builtin_amdgcn_wave_barrier();
-    const float2* D = Dsh[wv];
-    float qa[DMAX];
+  for (int i = 0; i < DM; ++i) qa[i] = 0.f;
+  for (int r0 = lane; r0 < n; r0 += 64 * UNR) {
+    float2 w[UNR][DM];
 #pragma unroll
-    for (int i = 0; i < DMAX; ++i) qa[i] = 0.f;
-    for (int r = lane; r < a.chi_r; r += 64) {
-      float2 w[DMAX];
+    for (int u = 0; u < UNR; ++u)
 #pragma unroll
-      for (int jj = 0; jj < DMAX; ++jj) w[jj] = jj < d ? Wrow[(size_t)jj * a.chi_r + r] : make_float2(0.f, 0.f);
+      for (int jj = 0; jj < DM; ++jj) {
+        const int r = r0 + 64 * u;
+        w[u][jj] = (jj < d && r < n) ? Wrow[(size_t)jj * n + r] : make_float2(0.f, 0.f);
+      }
+    // columns past chi_r add exact zeros
 #pragma unroll
-      for (int i = 0; i < DMAX; ++i) {
+    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+      for (int i = 0; i < DM; ++i) {
         if (i < d) {
           float xr = 0.f, xi = 0.f;
 #pragma unroll
-          for (int jj = 0; jj < DMAX; ++jj) {
+          for (int jj = 0; jj < DM; ++jj) {
             if (jj < d) {
               const float2 g = D[i * d + jj];
-              xr += g.x * w[jj].x - g.y * w[jj].y;
-              xi += g.x * w[jj].y + g.y * w[jj].x;
+              xr += g.x * w[u][jj].x - g.y * w[u][jj].y;
+              xi += g.x * w[u][jj].y + g.y * w[u][jj].x;
             }
           }
           qa[i] += xr * xr + xi * xi;
         }
       }
-    }
+  }
+  double q[DMAX];
 #pragma unroll
-    for (int i = 0; i < DMAX; ++i) {
-      double v = (double)qa[i];
+  for (int i = 0; i < DMAX; ++i) {
+    double v = i < DM ? (double)qa[i < DM ? i : 0] : 0.0;  // (the index stays in range when unrolled)
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-      q[i] = i < d ? v : 0.0;
-    }
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    q[i] = i < d ? v : 0.0;
   }
   // S = P_{d-1}, the last of the left-to-right prefix sums P_j = q_0 + .. + q_j
   double S = 0.0;
@@ -395,16 +398,13 @@ __global__ __launch_bounds__(256) void measure_kernel(const MeasureProb* probs, 
   const double lp_prev = *logp;
   const bool alive = !(lp_prev == -INFINITY);
   bool ok = alive && isfinite(S) && S > 0.0;
-
-  const uint64_t n = (uint64_t)(ch.n_offset + crow);
-  const double u = draw_uniform(n, a.site, seed, a.mps_id);
-
+  const double u = draw_uniform((uint64_t)(ch.n_offset + crow), a.site, seed, a.mps_id);
   int s = 0;
   double Pi = 0.0;
 #pragma unroll
   for (int i = 0; i < DMAX; ++i) {
-    Pi += q[i];                       // P_i, summed in the same order as S
-    if (i < d && u > Pi / S) ++s;     // C_i = P_i / S;  C_{d-1} == 1
+    Pi += q[i];                    // P_i, summed in the same order as S
+    if (i < d && u > Pi / S) ++s;  // C_i = P_i / S;  C_{d-1} == 1
   }
   if (s > d - 1) s = d - 1;
   double qs = 0.0;
@@ -414,7 +414,7 @@ __global__ __launch_bounds__(256) void measure_kernel(const MeasureProb* probs, 
   ok = ok && qs > 0.0;
   if (!ok) s = 0;
 
-  if (sl == 0) {
+  if (lane == 0) {
     a.outcomes[(size_t)crow * a.M + a.site] = ok ? s : -1;
     *logp = ok ? lp_prev + log(qs / S) : -INFINITY;
     if (alive && !ok) atomicAdd(nflag, 1);
@@ -429,86 +429,55 @@ __global__ __launch_bounds__(256) void measure_kernel(const MeasureProb* probs, 
     }
   }
 
-  const float2* src = Wrow + (size_t)s * a.chi_r;
-  LWriter<OUT> out(a, row);
-  if constexpr (OUT == kOutF16F6) {
-    // The record writer takes whole 16-K slices: each lane forms 8 complex
-    // values of the chosen branch (of W' = D(mu) W when displaced; zeros past
-    // chi_r and for a flagged sample), the same arithmetic per value as the
-    // other writers' paths below.
-    const float scale = ok ? (float)(1.0 / sqrt(qs)) : 0.f;
-    const float2* Ds = Dsh[wv] + s * d;
-    const int n8 = (a.chi_r + 7) >> 3;
-    for (int q8 = sl; q8 < n8; q8 += W) {
-      float2 v[8];
+  // the chosen branch W'_s = sum_j D[s][j] W_j, scaled by 1 / sqrt(q_s);
+  // zeros past chi_r and for a flagged sample
+  const float scale = ok ? (float)(1.0 / sqrt(qs)) : 0.f;
+  float2 g[DM];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int r = 8 * q8 + e;
-        float xr = 0.f, xi = 0.f;
-        if (ok && r < a.chi_r) {
-          if (disp) {
-            for (int jj = 0; jj < d; ++jj) {
-              const float2 g = Ds[jj], w = Wrow[(size_t)jj * a.chi_r + r];
-              xr += g.x * w.x - g.y * w.y;
-              xi += g.x * w.y + g.y * w.x;
+  for (int jj = 0; jj < DM; ++jj) g[jj] = jj < d ? D[s * d + jj] : make_float2(0.f, 0.f);
+  LWriter<OUT> out(a, row);
+  const int nq = (n + PC - 1) / PC;
+  const bool vec = (n & 1) == 0;  // every branch row is then 16-byte aligned at even r
+  for (int qp = lane; qp < nq; qp += 64) {
+    const int r0 = PC * qp;
+    float xr[PC], xi[PC];
+#pragma unroll
+    for (int e = 0; e < PC; ++e) xr[e] = xi[e] = 0.f;
+    if (ok) {
+      const bool full = vec && r0 + PC <= n;
+#pragma unroll
+      for (int jj = 0; jj < DM; ++jj) {
+        if (jj < d) {
+          float2 w[PC];
+          const float2* src = Wrow + (size_t)jj * n + r0;
+          if (full) {
+#pragma unroll
+            for (int e = 0; e < PC; e += 2) {
+              const float4 p4 = *reinterpret_cast<const float4*>(src + e);
+              w[e] = make_float2(p4.x, p4.y);
+              w[e + 1] = make_float2(p4.z, p4.w);
             }
           } else {
-            const float2 w = src[r];
-            xr = w.x;
-            xi = w.y;
+#pragma unroll
+            for (int e = 0; e < PC; ++e) w[e] = r0 + e < n ? src[e] : make_float2(0.f, 0.f);
           }
-          xr = __fmul_rn(xr, scale);
-          xi = __fmul_rn(xi, scale);
+#pragma unroll
+          for (int e = 0; e < PC; ++e) {
+            xr[e] += g[jj].x * w[e].x - g[jj].y * w[e].y;
+            xi[e] += g[jj].x * w[e].y + g[jj].y * w[e].x;
+          }
         }
-        v[e] = make_float2(xr, xi);
       }
-      out.put8(8 * q8, v);
     }
-    out.pad_from(16 * n8, sl, W);
-    return;
-  } else if (ok && !disp) {
-    // Each lane takes 4 consecutive complex of the chosen branch (zeros past
-    // chi_r), so the 16-bit formats get whole 16-byte stores.
-    const float scale = (float)(1.0 / sqrt(qs));
-    const int nq = (a.chi_r + 3) >> 2;
-    const bool even = (a.chi_r & 1) == 0;  // src is then 16-byte aligned at every even r
-#pragma unroll 2
-    for (int q4 = sl; q4 < nq; q4 += W) {
-      const int r4 = 4 * q4;
-      float2 v[4];
-      if (even && r4 + 4 <= a.chi_r) {
-        const float4 p0 = *reinterpret_cast<const float4*>(src + r4);
-        const float4 p1 = *reinterpret_cast<const float4*>(src + r4 + 2);
-        v[0] = make_float2(p0.x, p0.y);
-        v[1] = make_float2(p0.z, p0.w);
-        v[2] = make_float2(p1.x, p1.y);
-        v[3] = make_float2(p1.z, p1.w);
-      } else {
+    float2 v[PC];
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) v[jj] = r4 + jj < a.chi_r ? src[r4 + jj] : make_float2(0.f, 0.f);
-      }
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) v[jj] = make_float2(__fmul_rn(v[jj].x, scale), __fmul_rn(v[jj].y, scale));
-      out.put4(r4, v);
-    }
-    out.pad_from(8 * nq, sl, W);
-  } else if (ok) {
-    // chosen branch of W' = D(mu) W
-    const float scale = (float)(1.0 / sqrt(qs));
-    const float2* Ds = Dsh[wv] + s * d;
-    for (int r = lane; r < a.chi_r; r += 64) {
-      float xr = 0.f, xi = 0.f;
-      for (int jj = 0; jj < d; ++jj) {
-        const float2 g = Ds[jj], w = Wrow[(size_t)jj * a.chi_r + r];
-        xr += g.x * w.x - g.y * w.y;
-        xi += g.x * w.y + g.y * w.x;
-      }
-      out.put(r, __fmul_rn(xr, scale), __fmul_rn(xi, scale));
-    }
-  } else {
-    for (int r = sl; r < a.chi_r; r += W) out.put(r, 0.f, 0.f);
+    for (int e = 0; e < PC; ++e) v[e] = make_float2(__fmul_rn(xr[e], scale), __fmul_rn(xi[e], scale));
+    if constexpr (PC == 8)
+      out.put8(r0, v);
+    else
+      out.put4(r0, v);
   }
-  if constexpr (OUT != kOutF16F6) out.pad(a, sl, W);
+  out.pad_from(2 * PC * nq, lane, 64);
 }
 
 // Measurement without displacement, in two phases per workgroup of 64 rows:
@@ -521,8 +490,9 @@ __global__ __launch_bounds__(256) void measure_kernel(const MeasureProb* probs, 
 //      handled by min(meas_lanes(chi_r), 16) lanes, each taking 4
 //      consecutive complex at a time, over a flat loop of (row, piece) so
 //      that several rows' loads are in flight together.
-// The arithmetic, its order and every stored value are those of the
-// one-group-per-row form used with displacement above.
+// The decision takes the same steps, in the same order, as in the displaced
+// kernel above, with the branch weights summed from the contraction's
+// partial weights instead of formed from W'.
 // RPB rows per workgroup: 64, or 16 when a launch of 64-row workgroups would
 // leave CUs idle (few rows per chunk at a large bond: 8192 rows make 128
 // workgroups of 64 rows for 256 CUs).  A row's results do not depend on RPB.
@@ -783,11 +753,15 @@ hipError_t launch_zero_int(int* p, int n, hipStream_t s) {
 constexpr long long kMeasureFullGrid = 512;
 
 template <int OUT>
-void launch_measure_t(bool displaced, int grid_rows, int nprob, const MeasureProb* probs, const ChunkArgs* ch,
-                      uint64_t seed, int* nflag, hipStream_t s) {
-  if (displaced)  // one wave per row
-    hipLaunchKernelGGL((measure_kernel<OUT, true>), dim3((grid_rows + 3) / 4, nprob), dim3(256), 0, s, probs, ch,
-                       seed, nflag);
+void launch_measure_t(bool displaced, int dmax, int grid_rows, int nprob, const MeasureProb* probs,
+                      const ChunkArgs* ch, uint64_t seed, int* nflag, hipStream_t s) {
+  const dim3 g1((grid_rows + 3) / 4, nprob);  // displaced: one wave per row
+  if (displaced && dmax <= 4)
+    hipLaunchKernelGGL((measure_disp_kernel<OUT, 4>), g1, dim3(256), 0, s, probs, ch, seed, nflag);
+  else if (displaced && dmax <= 8)
+    hipLaunchKernelGGL((measure_disp_kernel<OUT, 8>), g1, dim3(256), 0, s, probs, ch, seed, nflag);
+  else if (displaced)
+    hipLaunchKernelGGL((measure_disp_kernel<OUT, DMAX>), g1, dim3(256), 0, s, probs, ch, seed, nflag);
   else if ((long long)((grid_rows + 63) / 64) * nprob >= kMeasureFullGrid)
     hipLaunchKernelGGL((measure_rows_kernel<OUT, 64>), dim3((grid_rows + 63) / 64, nprob), dim3(256), 0, s, probs,
                        ch, seed, nflag);
@@ -797,21 +771,21 @@ void launch_measure_t(bool displaced, int grid_rows, int nprob, const MeasurePro
 }
 
 hipError_t launch_measure(int form, const MeasureProb* probs, int nprob, const ChunkArgs* ch, int grid_rows,
-                          uint64_t seed, int* nflag, bool displaced, int rows_per_wave, hipStream_t s) {
-  (void)rows_per_wave;
+                          uint64_t seed, int* nflag, bool displaced, int dmax, hipStream_t s) {
   if (grid_rows <= 0 || nprob <= 0) return hipSuccess;
+  if (displaced && (dmax < 1 || dmax > DMAX)) return hipErrorInvalidValue;
   if (form == 0)
-    launch_measure_t<kOutF32>(displaced, grid_rows, nprob, probs, ch, seed, nflag, s);
+    launch_measure_t<kOutF32>(displaced, dmax, grid_rows, nprob, probs, ch, seed, nflag, s);
   else if (form == kBf16x3)
-    launch_measure_t<kOutBf16x2>(displaced, grid_rows, nprob, probs, ch, seed, nflag, s);
+    launch_measure_t<kOutBf16x2>(displaced, dmax, grid_rows, nprob, probs, ch, seed, nflag, s);
   else if (form == kFp16x3)
-    launch_measure_t<kOutF16x2>(displaced, grid_rows, nprob, probs, ch, seed, nflag, s);
+    launch_measure_t<kOutF16x2>(displaced, dmax, grid_rows, nprob, probs, ch, seed, nflag, s);
   else if (form == kFp16F8)
-    launch_measure_t<kOutF16F8>(displaced, grid_rows, nprob, probs, ch, seed, nflag, s);
+    launch_measure_t<kOutF16F8>(displaced, dmax, grid_rows, nprob, probs, ch, seed, nflag, s);
   else if (form == kFp16F6)
-    launch_measure_t<kOutF16F6>(displaced, grid_rows, nprob, probs, ch, seed, nflag, s);
+    launch_measure_t<kOutF16F6>(displaced, dmax, grid_rows, nprob, probs, ch, seed, nflag, s);
   else
-    launch_measure_t<kOutF16>(displaced, grid_rows, nprob, probs, ch, seed, nflag, s);
+    launch_measure_t<kOutF16>(displaced, dmax, grid_rows, nprob, probs, ch, seed, nflag, s);
   return hipGetLastError();
 }
 

@@ -249,7 +249,7 @@ struct Step {
   size_t ctab[2] = {0, 0}, tntab[2] = {0, 0};
   int blk_total = 0;  // packing blocks over all problems of the step
   int cm_total = 0;   // column-scale blocks (MPS_FP16F8, MPS_FP16F6)
-  int meas_rpw = 64;  // samples per wave in the measurement (set by the largest chi_r)
+  int dmax = 1;       // largest physical dimension of the step's problems
   size_t pack = 0, blk_start = 0, measure = 0, cm_start = 0;  // offsets in the table blob
   double flops_per_row = 0, meas_bytes_per_row = 0;
 };
@@ -677,10 +677,15 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
         }
         if (single) mp.mu = (const float2*)o.displace;
         ms.push_back(mp);
-        sp.meas_rpw = std::min(sp.meas_rpw, 64 / mps::meas_lanes(chr));
+        sp.dmax = std::max(sp.dmax, dk);
         sp.flops_per_row += 8.0 * (double)K * dk * chr;
-        // partial weights read + chosen branch read + new left vector write + outcome + logp read/write
-        sp.meas_bytes_per_row += (double)dk * T * 4 + 2.0 * chr * 8 + 4 + 16;
+        // partial weights read + chosen branch read + new left vector write +
+        // outcome + logp read/write; displaced: every branch of W read once
+        // (W' = D(mu) W) instead of the partial weights and one branch, and mu
+        if (single && o.displace)
+          sp.meas_bytes_per_row += (double)dk * chr * 8 + chr * 8.0 + 8 + 4 + 16;
+        else
+          sp.meas_bytes_per_row += (double)dk * T * 4 + 2.0 * chr * 8 + 4 + 16;
       }
       sp.nprob = (int)ms.size();
       for (int v = 0; v < 2; ++v) {
@@ -819,7 +824,7 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
     MPS_TRY(mark(k, 3, stream));
     MPS_TRY(mark(k, 4, stream));
     MPS_HIP(mps::launch_measure(form, (const mps::MeasureProb*)tp(sp.measure), sp.nprob, ch, grid_rows, seed, nflag,
-                                displaced, sp.meas_rpw, stream),
+                                displaced, sp.dmax, stream),
             "measurement launch");
     return mark(k, 5, stream);
   };

@@ -311,6 +311,44 @@ def test_displacement_parity(mpsmod, form):
     s.close()
 
 
+@pytest.mark.parametrize("form", PARITY_FORMS)
+def test_displacement_parity_ragged_bonds(mpsmod, form):
+    """Displacement with odd and ragged bonds (d=3 ramp 1, 3, 9, 27, 81, 99:
+    columns past the last whole piece, odd chi_r without 16-byte rows, a
+    weights pass whose last column block is partial)."""
+    from tests.parity_util import compare, upload
+    _say(f"displaced ragged sweep M=10 d=3 chi=99 N=300 {form}")
+    M, N = 10, 300
+    t = _chain(41, M, 3, 99)
+    rng = np.random.default_rng(6)
+    mu = ((rng.standard_normal((N, M)) + 1j * rng.standard_normal((N, M))) * 0.5).astype(np.complex64)
+    s = _sampler(mpsmod, form)
+    r = s.sample(upload(t), N, 12, emit_n=N, displace=torch.from_numpy(mu).cuda())
+    torch.cuda.synchronize()
+    g = {k: r[k].cpu().numpy() for k in ("outcomes", "logp", "probs", "u")}
+    rep = compare(t, 12, g, eps=EPS[form], displace=mu)
+    print(rep)
+    s.close()
+
+
+@pytest.mark.parametrize("form", ["fp32", "fp16f6"])
+def test_displacement_parity_large_physical_dimension(mpsmod, form):
+    """Displacement with d = 10 (the widest per-lane arrays, 16 levels)."""
+    from tests.parity_util import compare, upload
+    _say(f"displaced sweep M=6 d=10 chi=40 N=256 {form}")
+    M, N = 6, 256
+    t = _chain(43, M, 10, 40)
+    rng = np.random.default_rng(8)
+    mu = ((rng.standard_normal((N, M)) + 1j * rng.standard_normal((N, M))) * 0.6).astype(np.complex64)
+    s = _sampler(mpsmod, form)
+    r = s.sample(upload(t), N, 13, emit_n=N, displace=torch.from_numpy(mu).cuda())
+    torch.cuda.synchronize()
+    g = {k: r[k].cpu().numpy() for k in ("outcomes", "logp", "probs", "u")}
+    rep = compare(t, 13, g, eps=EPS[form], displace=mu)
+    print(rep)
+    s.close()
+
+
 def test_displaced_vacuum_poisson_on_gpu(mpsmod):
     """chi = 1 vacuum sites with displacement mu: the conditional probabilities
     are Poisson(|mu|^2) renormalised over the d levels (closed form)."""
