@@ -437,20 +437,22 @@ __global__ __launch_bounds__(256) void measure_disp_kernel(const MeasureProb* pr
   for (int jj = 0; jj < DM; ++jj) g[jj] = jj < d ? D[s * d + jj] : make_float2(0.f, 0.f);
   LWriter<OUT> out(a, row);
   const int nq = (n + PC - 1) / PC;
-  const bool vec = (n & 1) == 0;  // every branch row is then 16-byte aligned at even r
+  // chi_r a multiple of PC: every piece whole and 16-byte aligned, so the
+  // choice of load is uniform over the wave (no lane-dependent branch
+  // between the loads of a piece)
+  const bool whole = n % PC == 0;
   for (int qp = lane; qp < nq; qp += 64) {
     const int r0 = PC * qp;
     float xr[PC], xi[PC];
 #pragma unroll
     for (int e = 0; e < PC; ++e) xr[e] = xi[e] = 0.f;
     if (ok) {
-      const bool full = vec && r0 + PC <= n;
 #pragma unroll
       for (int jj = 0; jj < DM; ++jj) {
         if (jj < d) {
           float2 w[PC];
           const float2* src = Wrow + (size_t)jj * n + r0;
-          if (full) {
+          if (whole) {
 #pragma unroll
             for (int e = 0; e < PC; e += 2) {
               const float4 p4 = *reinterpret_cast<const float4*>(src + e);

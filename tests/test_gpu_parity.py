@@ -331,6 +331,26 @@ def test_displacement_parity_ragged_bonds(mpsmod, form):
     s.close()
 
 
+@pytest.mark.parametrize("form", ["fp32", "bf16x3", "fp16f6"])
+def test_displacement_parity_bond_above_register_rows(mpsmod, form):
+    """Displacement at right bonds up to 1100 (d=2 ramp 1, 2, .., 1024, 1100):
+    wide rows, and bonds that are and are not whole multiples of the
+    gather's piece (8 complex for fp16f6, 4 otherwise)."""
+    from tests.parity_util import compare, upload
+    _say(f"displaced sweep M=26 d=2 chi=1100 N=64 {form}")
+    M, N = 26, 64
+    t = _chain(47, M, 2, 1100)
+    rng = np.random.default_rng(10)
+    mu = ((rng.standard_normal((N, M)) + 1j * rng.standard_normal((N, M))) * 0.5).astype(np.complex64)
+    s = _sampler(mpsmod, form)
+    r = s.sample(upload(t), N, 14, emit_n=N, displace=torch.from_numpy(mu).cuda())
+    torch.cuda.synchronize()
+    g = {k: r[k].cpu().numpy() for k in ("outcomes", "logp", "probs", "u")}
+    rep = compare(t, 14, g, eps=EPS[form], displace=mu)
+    print(rep)
+    s.close()
+
+
 @pytest.mark.parametrize("form", ["fp32", "fp16f6"])
 def test_displacement_parity_large_physical_dimension(mpsmod, form):
     """Displacement with d = 10 (the widest per-lane arrays, 16 levels)."""
