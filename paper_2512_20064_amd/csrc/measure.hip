@@ -325,7 +325,7 @@ __device__ inline float2 displacement_entry(double mr, double mi, int i, int j) 
 // 8 or 16) sizes the per-lane arrays so that the loads of a step are all
 // issued before its arithmetic: UNR columns per lane at a time in the
 // weights pass, and in the gather a piece of PC consecutive complex of every
-// branch (16-byte loads when chi_r is even).
+// branch (16-byte loads when chi_r is a multiple of PC).
 template <int OUT, int DM>
 __global__ __launch_bounds__(256) void measure_disp_kernel(const MeasureProb* probs, const ChunkArgs* chp,
                                                            uint64_t seed, int* nflag) {
