@@ -426,7 +426,9 @@ def run_chain_bench(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": FORMS[args.precision]["dtype"],
         "data": "synthetic",
-        "config": {"workload": wname, "sites": M, "d": (4 if args.workload != "uneven" else "2..6"),
+        "config": {"workload": wname + (f", per-sample displacement (complex Gaussian, scale {args.displace})"
+                                        if args.displace > 0 else ""),
+                   "sites": M, "d": (4 if args.workload != "uneven" else "2..6"),
                    "chi": int(max(chi)), "samples_per_step": args.chunk,
                    "precision": args.precision, "tensor_bytes": distinct_bytes(dev),
                    "displace_sigma": args.displace or None},
