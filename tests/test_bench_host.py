@@ -84,3 +84,17 @@ def test_cpu_baseline_reports_threads_host_and_single_thread_leg():
     assert h["blas"] is None or h["blas"]["library"]
     s = r["small_chain_full"]
     assert s["value"] > 0 and s["single_thread_value"] > 0 and "N=4096" in s["workload"]
+
+
+def test_cpu_baseline_takes_the_displacements_of_a_displaced_run():
+    """With per-sample displacements the oracle legs run displaced too (the
+    same D(mu) per sample and site as the GPU run) and say so."""
+    import numpy as np
+    from paper_2512_20064_amd import synth
+    t, _, _ = synth.small_chain(2, M=8, d=2, chi_max=8)
+    rng = np.random.default_rng(3)
+    mu = (rng.standard_normal((64, 8)) + 1j * rng.standard_normal((64, 8))) * 0.3
+    r = bench.cpu_baseline(t, 5, 64, 6, 16, mu=mu)
+    assert r["value"] > 0 and "displaced" in r["sample"]
+    assert "displaced" not in bench.cpu_baseline(t, 5, 64, 6, 16)["sample"]
+
