@@ -482,6 +482,190 @@ __global__ __launch_bounds__(256) void measure_disp_kernel(const MeasureProb* pr
   out.pad_from(2 * PC * nq, lane, 64);
 }
 
+// The displaced measurement for d <= 4 and chi_r <= 1024 with W read once:
+// two waves per sample (a workgroup of four waves takes two samples), lane
+// l of the sample's wave h holding the 8 consecutive complex from
+// 512 h + 8 l of every branch in registers from the weights pass to the
+// gather.  Each wave's FP32 lane sums are added in FP64 by the fixed
+// butterfly, then the two waves' sums (first + second) in LDS; one lane per
+// sample makes the decision.  With chi_r a multiple of 8 every piece is
+// whole and 16-byte aligned, and a lane whose piece starts past chi_r reads
+// the row's last piece instead (in bounds; masked out of the weights and
+// not written), so the loads carry no lane-dependent branch.
+template <int OUT>
+__global__ __launch_bounds__(256) void measure_disp_pair_kernel(const MeasureProb* probs, const ChunkArgs* chp,
+                                                                uint64_t seed, int* nflag) {
+  constexpr int DM = 4;
+  __shared__ float2 Dsh[2][DM * DM];
+  __shared__ double qsh[4][DM];
+  __shared__ int s_sh[2];
+  __shared__ float scale_sh[2];
+  const ChunkArgs ch = *chp;
+  const MeasureProb a = probs[blockIdx.y];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int rl = wv >> 1, h = wv & 1;
+  const int row = blockIdx.x * 2 + rl;
+  if (blockIdx.x * 2 >= ch.rows) return;  // the whole workgroup
+  const bool live = row < ch.rows;         // uniform over the wave
+  const int d = a.d, n = a.chi_r;
+  const float2* Wrow = a.W + (size_t)(live ? row : 0) * d * n;
+  const int r0 = 512 * h + 8 * lane;
+  const bool valid = live && r0 < n;
+
+  float2 w[DM][8];
+#pragma unroll
+  for (int jj = 0; jj < DM; ++jj)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) w[jj][e] = make_float2(0.f, 0.f);
+  if (live) {
+    if ((n & 7) == 0) {
+      const int rc = min(r0, n - 8);
+#pragma unroll
+      for (int jj = 0; jj < DM; ++jj) {
+        if (jj < d) {
+          const float4* src = reinterpret_cast<const float4*>(Wrow + (size_t)jj * n + rc);
+#pragma unroll
+          for (int e = 0; e < 8; e += 2) {
+            const float4 p4 = src[e >> 1];
+            w[jj][e] = make_float2(p4.x, p4.y);
+            w[jj][e + 1] = make_float2(p4.z, p4.w);
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int jj = 0; jj < DM; ++jj)
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          if (jj < d && r0 + e < n) w[jj][e] = Wrow[(size_t)jj * n + r0 + e];
+    }
+  }
+  // D(mu) while the loads are in flight (the sample's first wave)
+  if (live && h == 0) {
+    const float2 mu = a.mu[(size_t)(ch.c0 + row) * a.M + a.site];
+    for (int t = lane; t < d * d; t += 64) Dsh[rl][t] = displacement_entry(mu.x, mu.y, t / d, t % d);
+  }
+  __syncthreads();
+
+  // branch weights of W' (columns past chi_r left out)
+  if (live) {
+    const float2* D = Dsh[rl];
+    float qa[DM];
+#pragma unroll
+    for (int i = 0; i < DM; ++i) qa[i] = 0.f;
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+#pragma unroll
+      for (int i = 0; i < DM; ++i) {
+        if (i < d) {
+          float xr = 0.f, xi = 0.f;
+#pragma unroll
+          for (int jj = 0; jj < DM; ++jj) {
+            if (jj < d) {
+              const float2 g = D[i * d + jj];
+              xr += g.x * w[jj][e].x - g.y * w[jj][e].y;
+              xi += g.x * w[jj][e].y + g.y * w[jj][e].x;
+            }
+          }
+          qa[i] += valid ? xr * xr + xi * xi : 0.f;
+        }
+      }
+#pragma unroll
+    for (int i = 0; i < DM; ++i) {
+      double v = (double)qa[i];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (lane == 0) qsh[wv][i] = v;
+    }
+  }
+  __syncthreads();
+
+  // the decision, one lane per sample
+  if (live && h == 0 && lane == 0) {
+    const int64_t crow = ch.c0 + row;  // row within the call
+    double* const logp = a.logp + (a.logp_in_call ? crow : row);
+    double q[DMAX];
+#pragma unroll
+    for (int i = 0; i < DMAX; ++i) {
+      const int k = i < DM ? i : 0;  // (the index stays in range when unrolled)
+      q[i] = i < DM && i < d ? qsh[2 * rl][k] + qsh[2 * rl + 1][k] : 0.0;
+    }
+    // S = P_{d-1}, the last of the left-to-right prefix sums P_j = q_0 + .. + q_j
+    double S = 0.0;
+#pragma unroll
+    for (int i = 0; i < DMAX; ++i)
+      if (i < d) S += q[i];
+    const double lp_prev = *logp;
+    const bool alive = !(lp_prev == -INFINITY);
+    bool ok = alive && isfinite(S) && S > 0.0;
+    const double u = draw_uniform((uint64_t)(ch.n_offset + crow), a.site, seed, a.mps_id);
+    int s = 0;
+    double Pi = 0.0;
+#pragma unroll
+    for (int i = 0; i < DMAX; ++i) {
+      Pi += q[i];                    // P_i, summed in the same order as S
+      if (i < d && u > Pi / S) ++s;  // C_i = P_i / S;  C_{d-1} == 1
+    }
+    if (s > d - 1) s = d - 1;
+    double qs = 0.0;
+#pragma unroll
+    for (int i = 0; i < DMAX; ++i)
+      if (i == s) qs = q[i];
+    ok = ok && qs > 0.0;
+    if (!ok) s = 0;
+    a.outcomes[(size_t)crow * a.M + a.site] = ok ? s : -1;
+    *logp = ok ? lp_prev + log(qs / S) : -INFINITY;
+    if (alive && !ok) atomicAdd(nflag, 1);
+    if (crow < a.emit_n) {
+      if (a.emit_u) a.emit_u[(size_t)crow * a.M + a.site] = u;
+      if (a.emit_probs) {
+        double* ep = a.emit_probs + ((size_t)crow * a.M + a.site) * a.emit_dmax;
+#pragma unroll
+        for (int i = 0; i < DMAX; ++i)
+          if (i < d && i < a.emit_dmax) ep[i] = ok ? q[i] / S : NAN;
+      }
+    }
+    s_sh[rl] = ok ? s : -1;
+    scale_sh[rl] = ok ? (float)(1.0 / sqrt(qs)) : 0.f;
+  }
+  __syncthreads();
+  if (!live) return;
+
+  // the chosen branch W'_s = sum_j D[s][j] W_j from the registers, scaled by
+  // 1 / sqrt(q_s); zeros past chi_r and for a flagged sample
+  const int s = s_sh[rl];
+  const bool ok = s >= 0;
+  const float scale = scale_sh[rl];
+  float2 g[DM];
+#pragma unroll
+  for (int jj = 0; jj < DM; ++jj) g[jj] = ok && jj < d ? Dsh[rl][s * d + jj] : make_float2(0.f, 0.f);
+  LWriter<OUT> out(a, row);
+  if (r0 < n) {
+    float2 v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      float xr = 0.f, xi = 0.f;
+#pragma unroll
+      for (int jj = 0; jj < DM; ++jj) {
+        if (jj < d) {
+          xr += g[jj].x * w[jj][e].x - g[jj].y * w[jj][e].y;
+          xi += g[jj].x * w[jj][e].y + g[jj].y * w[jj][e].x;
+        }
+      }
+      v[e] = r0 + e < n ? make_float2(__fmul_rn(xr, scale), __fmul_rn(xi, scale)) : make_float2(0.f, 0.f);
+    }
+    if constexpr (OUT == kOutF16F6) {
+      out.put8(r0, v);
+    } else {
+      const float2 lo4[4] = {v[0], v[1], v[2], v[3]}, hi4[4] = {v[4], v[5], v[6], v[7]};
+      out.put4(r0, lo4);
+      out.put4(r0 + 4, hi4);
+    }
+  }
+  out.pad_from(16 * ((n + 7) >> 3), lane + 64 * h, 128);
+}
+
 // Measurement without displacement, in two phases per workgroup of 64 rows:
 //   1. wave 0 takes one row per lane and makes the per-row decision (branch
 //      weights from the partial sums, S, the Philox uniform, the outcome,
@@ -755,10 +939,13 @@ hipError_t launch_zero_int(int* p, int n, hipStream_t s) {
 constexpr long long kMeasureFullGrid = 512;
 
 template <int OUT>
-void launch_measure_t(bool displaced, int dmax, int grid_rows, int nprob, const MeasureProb* probs,
+void launch_measure_t(bool displaced, int dmax, int chir_max, int grid_rows, int nprob, const MeasureProb* probs,
                       const ChunkArgs* ch, uint64_t seed, int* nflag, hipStream_t s) {
   const dim3 g1((grid_rows + 3) / 4, nprob);  // displaced: one wave per row
-  if (displaced && dmax <= 4)
+  if (displaced && dmax <= 4 && chir_max <= 1024)
+    hipLaunchKernelGGL((measure_disp_pair_kernel<OUT>), dim3((grid_rows + 1) / 2, nprob), dim3(256), 0, s, probs, ch,
+                       seed, nflag);
+  else if (displaced && dmax <= 4)
     hipLaunchKernelGGL((measure_disp_kernel<OUT, 4>), g1, dim3(256), 0, s, probs, ch, seed, nflag);
   else if (displaced && dmax <= 8)
     hipLaunchKernelGGL((measure_disp_kernel<OUT, 8>), g1, dim3(256), 0, s, probs, ch, seed, nflag);
@@ -773,21 +960,21 @@ void launch_measure_t(bool displaced, int dmax, int grid_rows, int nprob, const 
 }
 
 hipError_t launch_measure(int form, const MeasureProb* probs, int nprob, const ChunkArgs* ch, int grid_rows,
-                          uint64_t seed, int* nflag, bool displaced, int dmax, hipStream_t s) {
+                          uint64_t seed, int* nflag, bool displaced, int dmax, int chir_max, hipStream_t s) {
   if (grid_rows <= 0 || nprob <= 0) return hipSuccess;
   if (displaced && (dmax < 1 || dmax > DMAX)) return hipErrorInvalidValue;
   if (form == 0)
-    launch_measure_t<kOutF32>(displaced, dmax, grid_rows, nprob, probs, ch, seed, nflag, s);
+    launch_measure_t<kOutF32>(displaced, dmax, chir_max, grid_rows, nprob, probs, ch, seed, nflag, s);
   else if (form == kBf16x3)
-    launch_measure_t<kOutBf16x2>(displaced, dmax, grid_rows, nprob, probs, ch, seed, nflag, s);
+    launch_measure_t<kOutBf16x2>(displaced, dmax, chir_max, grid_rows, nprob, probs, ch, seed, nflag, s);
   else if (form == kFp16x3)
-    launch_measure_t<kOutF16x2>(displaced, dmax, grid_rows, nprob, probs, ch, seed, nflag, s);
+    launch_measure_t<kOutF16x2>(displaced, dmax, chir_max, grid_rows, nprob, probs, ch, seed, nflag, s);
   else if (form == kFp16F8)
-    launch_measure_t<kOutF16F8>(displaced, dmax, grid_rows, nprob, probs, ch, seed, nflag, s);
+    launch_measure_t<kOutF16F8>(displaced, dmax, chir_max, grid_rows, nprob, probs, ch, seed, nflag, s);
   else if (form == kFp16F6)
-    launch_measure_t<kOutF16F6>(displaced, dmax, grid_rows, nprob, probs, ch, seed, nflag, s);
+    launch_measure_t<kOutF16F6>(displaced, dmax, chir_max, grid_rows, nprob, probs, ch, seed, nflag, s);
   else
-    launch_measure_t<kOutF16>(displaced, dmax, grid_rows, nprob, probs, ch, seed, nflag, s);
+    launch_measure_t<kOutF16>(displaced, dmax, chir_max, grid_rows, nprob, probs, ch, seed, nflag, s);
   return hipGetLastError();
 }
 

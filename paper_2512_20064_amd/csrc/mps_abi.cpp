@@ -250,6 +250,7 @@ struct Step {
   int blk_total = 0;  // packing blocks over all problems of the step
   int cm_total = 0;   // column-scale blocks (MPS_FP16F8, MPS_FP16F6)
   int dmax = 1;       // largest physical dimension of the step's problems
+  int chir_max = 1;   // and largest right bond
   size_t pack = 0, blk_start = 0, measure = 0, cm_start = 0;  // offsets in the table blob
   double flops_per_row = 0, meas_bytes_per_row = 0;
 };
@@ -678,6 +679,7 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
         if (single) mp.mu = (const float2*)o.displace;
         ms.push_back(mp);
         sp.dmax = std::max(sp.dmax, dk);
+        sp.chir_max = std::max(sp.chir_max, chr);
         sp.flops_per_row += 8.0 * (double)K * dk * chr;
         // partial weights read + chosen branch read + new left vector write +
         // outcome + logp read/write; displaced: every branch of W read once
@@ -824,7 +826,7 @@ int run_sweep(mps_ctx* h, std::vector<Chain>& chains, int64_t N, int64_t n_offse
     MPS_TRY(mark(k, 3, stream));
     MPS_TRY(mark(k, 4, stream));
     MPS_HIP(mps::launch_measure(form, (const mps::MeasureProb*)tp(sp.measure), sp.nprob, ch, grid_rows, seed, nflag,
-                                displaced, sp.dmax, stream),
+                                displaced, sp.dmax, sp.chir_max, stream),
             "measurement launch");
     return mark(k, 5, stream);
   };

@@ -234,9 +234,9 @@ hipError_t launch_colscale(const PackProb* probs, const int* cm_start, int nprob
 hipError_t launch_contract_lp(int form, int tile, const ContractLpProb* probs, const int* tn_start, int nprob,
                               int tn_total, const ChunkArgs* ch, int grid_rows, int group_m, hipStream_t s);
 // displaced: the problems carry per-sample displacements (MeasureProb::mu);
-// dmax: the largest physical dimension d of the problems (1 .. 16; sizes
-// the displaced kernel's per-lane arrays).
+// dmax, chir_max: the largest physical dimension d (1 .. 16) and right bond
+// of the problems (they pick the displaced kernel's variant).
 hipError_t launch_measure(int form, const MeasureProb* probs, int nprob, const ChunkArgs* ch, int grid_rows,
-                          uint64_t seed, int* nflag, bool displaced, int dmax, hipStream_t s);
+                          uint64_t seed, int* nflag, bool displaced, int dmax, int chir_max, hipStream_t s);
 
 }  // namespace mps

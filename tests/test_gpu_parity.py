@@ -315,10 +315,11 @@ def test_displacement_parity(mpsmod, form):
 def test_displacement_parity_ragged_bonds(mpsmod, form):
     """Displacement with odd and ragged bonds (d=3 ramp 1, 3, 9, 27, 81, 99:
     columns past the last whole piece, odd chi_r without 16-byte rows, a
-    weights pass whose last column block is partial)."""
+    weights pass whose last column block is partial) and an odd number of
+    samples (a workgroup of two samples with one past the chunk)."""
     from tests.parity_util import compare, upload
-    _say(f"displaced ragged sweep M=10 d=3 chi=99 N=300 {form}")
-    M, N = 10, 300
+    _say(f"displaced ragged sweep M=10 d=3 chi=99 N=301 {form}")
+    M, N = 10, 301
     t = _chain(41, M, 3, 99)
     rng = np.random.default_rng(6)
     mu = ((rng.standard_normal((N, M)) + 1j * rng.standard_normal((N, M))) * 0.5).astype(np.complex64)
