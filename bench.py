@@ -322,6 +322,11 @@ def run_chain_bench(args):
     tuned = {}
     tiles = {}
     mu = None
+    # the displaced measurement keeps a sample's rows in registers for
+    # d <= 4 and bonds <= 1024 (two waves per sample), else one wave per sample
+    dl = d if isinstance(d, (list, tuple)) else [d] * M
+    disp_kernel = ("measure_disp_pair_kernel" if max(dl) <= 4 and max(chi) <= 1024
+                   else "measure_disp_kernel")
     if args.displace > 0:
         # per-sample displacements of the GBS variant (complex Gaussian, each
         # component of standard deviation sigma / sqrt(2)), one row per
@@ -394,7 +399,7 @@ def run_chain_bench(args):
         if not args.no_profile and c_ms > 0:
             out["roofline"] = roofline_of(form, c_fl, c_n, c_ms, dt, m_ms, p_ms, args.chunk, args.chi,
                                           m_bytes=m_b, m_n=m_n,
-                                          m_kernel="measure_disp_kernel" if mu is not None else "measure_rows_kernel")
+                                          m_kernel=disp_kernel if mu is not None else "measure_rows_kernel")
         elif not args.no_profile and f_ms > 0:
             out["roofline"] = roofline_small(f_fl, f_n, f_ms, dt)
         return out
