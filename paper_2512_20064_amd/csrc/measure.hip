@@ -13,9 +13,9 @@
 //
 // With a per-sample displacement mu (MPS-based GBS simulation, Section
 // 3.4.1) W is first replaced by D(mu) W over the physical index; D is built
-// per sample from the closed form of Eq. 7 into the wave's LDS (the paper
-// computes a batch of them with the batch index last; here each wave builds
-// its own sample's D next to the data it transforms), and the branch weights
+// per sample from the closed form of Eq. 7 into LDS (the paper computes a
+// batch of them with the batch index last; here the sample's own waves build
+// its D next to the data it transforms), and the branch weights
 // are then formed from W' directly instead of from the contraction's
 // partial sums.
 //
@@ -29,8 +29,9 @@
 // one lane per row makes the decision (the scalar FP64 and 64-bit integer
 // work, once per row), then groups of min(meas_lanes(chi_r), 16) lanes (down
 // to one lane for chi_r <= 4) gather the chosen branches.  With displacement
-// (measure_disp_kernel) one wave measures one row: it builds that row's D in
-// its LDS and forms the weights from W' directly.
+// a row's D is built in LDS and the weights are formed from W' directly: two
+// waves per row with the row held in registers (measure_disp_pair_kernel,
+// d <= 4 and chi_r <= 1024), else one wave per row (measure_disp_kernel).
 
 #include "e2m3.h"
 #include "philox.h"
