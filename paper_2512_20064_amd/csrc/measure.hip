@@ -654,7 +654,7 @@ __global__ __launch_bounds__(256) void measure_disp_pair_kernel(const MeasurePro
           xi += g[jj].x * w[jj][e].y + g[jj].y * w[jj][e].x;
         }
       }
-      v[e] = r0 + e < n ? make_float2(__fmul_rn(xr, scale), __fmul_rn(xi, scale)) : make_float2(0.f, 0.f);
+      v[e] = ok && r0 + e < n ? make_float2(__fmul_rn(xr, scale), __fmul_rn(xi, scale)) : make_float2(0.f, 0.f);
     }
     if constexpr (OUT == kOutF16F6) {
       out.put8(r0, v);

@@ -234,6 +234,31 @@ def test_non_finite_site_entry_flags_every_sample(mpsmod, form, bad):
     assert np.all(np.isneginf(g["logp"]))
 
 
+@pytest.mark.parametrize("form", ["fp32", "fp16f6"])
+def test_non_finite_site_entry_with_displacement(mpsmod, form):
+    """The same with per-sample displacement (D(mu) W is NaN for every
+    sample as well): every sample flagged at site 3, the earlier sites as in
+    the displaced run without the bad entry."""
+    from tests.parity_util import upload
+    _say(f"non-finite site entry with displacement at site 3 {form}")
+    M, N = 8, 400
+    t = _chain(14, M, 3, 9)
+    rng = np.random.default_rng(12)
+    mu = torch.from_numpy(((rng.standard_normal((N, M)) + 1j * rng.standard_normal((N, M))) * 0.4)
+                          .astype(np.complex64)).cuda()
+    s = _sampler(mpsmod, form)
+    ref = s.sample(upload(t), N, 1, displace=mu)
+    bad = [x.copy() for x in t]
+    bad[3][1, 0, 2] = np.complex64(complex(float("nan"), 0.0))
+    g = s.sample(upload(bad), N, 1, displace=mu)
+    torch.cuda.synchronize()
+    assert g["status"] == mpsmod.MPS_ENUMERIC and s.stats.flagged == N
+    out, out_ref = g["outcomes"].cpu().numpy(), ref["outcomes"].cpu().numpy()
+    assert np.all(out[:, 3:] == -1) and np.array_equal(out[:, :3], out_ref[:, :3])
+    assert np.all(np.isneginf(g["logp"].cpu().numpy()))
+    s.close()
+
+
 def test_empty_and_memory_cap(mpsmod):
     _say("N=0 and max_device_bytes forcing small chunks")
     t = _chain(15, 6, 4, 16)
