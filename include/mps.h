@@ -191,7 +191,10 @@ typedef struct {
   double measure_ms;
   double pack_ms;
   double contract_flops;      /* algorithmic flops: 8 * rows * chi_l * d * chi_r summed */
-  double measure_bytes;       /* algorithmic bytes of the measurement launches      */
+  double measure_bytes;       /* algorithmic bytes of the measurement launches:     */
+                              /* partial weights, the chosen branch and the next    */
+                              /* left vector; with displacement every branch of W   */
+                              /* (read once) and mu instead of the partial weights  */
   int64_t n_chunk;            /* chunk size the last call used                      */
   int64_t flagged;            /* samples that met S <= 0 or non-finite S            */
   int64_t scratch_bytes;      /* device scratch held by the handle                  */
